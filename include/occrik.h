@@ -1,0 +1,239 @@
+/*
+ * occrik.h -- C ABI of the MI355X (gfx950) occ-RI-K exact-exchange library.
+ *
+ * The library builds the exact-exchange contribution of k-point Gaussian
+ * planewave (GPW) solids with the occ-RI-K algorithm of Lee, Rettig, Feng,
+ * Epifanovsky and Head-Gordon, "Faster Exact Exchange for Solids via
+ * occ-RI-K" (arXiv 2207.09028).  Section and equation names below are the
+ * paper's.
+ *
+ * For one cell, a Gamma-centred k-mesh {k} and a uniform real-space grid, a
+ * build takes the occupied coefficients C_{mu i}(k) and returns
+ *
+ *   K_{mu j}(k)  = -(dV/N_k) sum_r chi*_{mu k}(r) W_{j k}(r)           (Sec. II.D, Alg. 3)
+ *       W_{j k}(r) = sum_{k', i} psi_{i k'}(r) V_{i k', j k}(r)         (eq. occrikinterm)
+ *       V_{i k', j k} = potential of psi*_{i k'} psi_{j k} fitted by
+ *                       plane waves G + q, q = k - k'                    (eqs. aodf, Vrao, VGao)
+ *       psi_{i k}(r) = sum_mu C_{mu i}(k) chi_{mu k}(r)                  (eq. occmo)
+ *       chi_{mu k}(r) = sum_T e^{ik.T} phi_mu(r - R_mu - T)              (Sec. II.A, Bloch AO;
+ *                       the 1/sqrt(N_k) is dropped, orbitals are normalised per cell)
+ *   K_ij(k)      = C(k)^H K_{mu j}(k)                                   (occupied block)
+ *   K~(k)        = K_mu(k) K_ij(k)^{-1} K_mu(k)^H                        (eq. occrikop, assembled
+ *                  through L L^H = -K_ij, xi = K_mu L^{-H}, K~ = -xi xi^H)
+ *   E_x          = (1/2N_k) sum_k Re tr K_ij(k)                         (Sec. II.A, E_K / N_k:
+ *                  per cell and per spin channel)
+ *
+ * Units are bohr and hartree.  dV = Omega / N_g.  All arrays are row-major;
+ * complex numbers are interleaved (re, im) pairs of doubles.
+ *
+ * Conventions (both sides of every parity test use them):
+ *   grid point   r_n = sum_d (n_d / N_d) a_d, row-major over (n_1, n_2, n_3)
+ *   k-point      k = sum_d (kappa_d / M_d) b_d, kappa_d in [0, M_d), row-major
+ *   pair momenta q = k - k' from the fractional k-points, never wrapped
+ *   DFT indices  0..N/2-1, -N/2..-1 (even N: the Nyquist bin is -N/2)
+ *   AO order     shells in the given order; cartesian components of a shell
+ *                lexicographic with x^l first (xx, xy, xz, yy, yz, zz for l = 2);
+ *                each component normalised as an isolated function
+ *   lattice sum  an image T of a shell is kept when |R + T - c| <= rho + r_s, c
+ *                the cell centre, rho the cell circumradius about c, r_s the
+ *                radius where N_s r^l exp(-alpha r^2) drops to lattice_tol
+ *
+ * Ownership: the caller owns every input and output buffer; a plan owns its
+ * device workspaces (the Bloch AOs on the grid, the occupied orbitals, the W
+ * accumulators and the FFT exchange buffer) and frees them in
+ * occrik_plan_destroy.  A plan is bound to one device and one HIP stream and
+ * is not re-entrant: calls on one plan must not overlap.
+ *
+ * Errors: every entry point returns an occrik_status and never throws,
+ * aborts or prints.  Outputs are unspecified when the status is not
+ * OCCRIK_OK.  occrik_last_error_message() returns a thread-local description
+ * of the last failure.
+ */
+#ifndef OCCRIK_H
+#define OCCRIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCCRIK_OK = 0,
+    OCCRIK_ERR_INVALID_ARG = 1,   /* a null pointer, a size out of range, an inconsistent input */
+    OCCRIK_ERR_UNSUPPORTED = 2,   /* a grid size that is not 2^a 3^b 5^c in the supported set, l > 3 */
+    OCCRIK_ERR_OOM = 3,           /* device memory (or the caller's mem_budget) exhausted */
+    OCCRIK_ERR_NOT_PD = 4,        /* -K_ij(k) not positive definite; occrik_last_error_k gives k */
+    OCCRIK_ERR_NONFINITE = 5,     /* NaN or Inf in C */
+    OCCRIK_ERR_DEVICE = 6,        /* a HIP runtime error */
+    OCCRIK_ERR_STATE = 7          /* call out of order (e.g. occrik_grad before a build) */
+} occrik_status;
+
+/* Reciprocal-space Coulomb kernels f(x), x = |G + q| (paper eq. recipcoul). */
+enum {
+    OCCRIK_KERNEL_COULOMB = 0,    /* 4 pi / x^2;                 x = 0 term zeroed */
+    OCCRIK_KERNEL_ERF_LR = 1,     /* 4 pi / x^2 exp(-x^2/4w^2);  x = 0 term zeroed */
+    OCCRIK_KERNEL_ERFC_SR = 2     /* 4 pi / x^2 (1 - exp(-x^2/4w^2)); x = 0 term pi / w^2 */
+};
+
+/* Treatment of the even-N Nyquist planes in the kernel multiply.
+ * FFTFREQ:   f(|G_m + q|) with m the numpy frequency (Nyquist component -N/2).
+ * SYMMETRIC: on Nyquist planes the mean of f at G_m + q and at the mirror index
+ *            with those components at +N/2.  E_x is identical in both modes;
+ *            only SYMMETRIC makes 2 K_{mu j} / N_k the exact gradient of E_x and
+ *            the (k, k', i, j) <-> (k', k, j, i) pair potentials exact complex
+ *            conjugates, which the build uses to halve the FFT count. */
+enum { OCCRIK_NYQUIST_FFTFREQ = 0, OCCRIK_NYQUIST_SYMMETRIC = 1 };
+
+/* Arithmetic of the grid-side work (collocated AOs, orbitals, FFTs, W, the two
+ * grid contractions).  K_ij, the Cholesky factorisation, the assembly and the
+ * energy reduction are FP64 in every mode. */
+enum {
+    OCCRIK_PREC_FP64 = 0,         /* complex128 grid data, FP64 FFTs and contractions */
+    OCCRIK_PREC_FP32 = 1,         /* complex64 grid data, FP32 FFTs, FP32 contractions */
+    OCCRIK_PREC_FP32_SPLIT = 2    /* complex64 grid data, FP32 FFTs, contractions on
+                                     bf16 matrix cores with 3-term operand splitting
+                                     and FP32 accumulation */
+};
+
+typedef struct {
+    double lattice[9];            /* rows a_1, a_2, a_3 in bohr, row-major */
+    int32_t natm;
+    const double *atom_frac;      /* host [natm][3], fractional coordinates */
+} occrik_cell;
+
+typedef struct {
+    int32_t nshell;
+    const int32_t *shell_atom;    /* host [nshell], index into the cell's atoms */
+    const int32_t *shell_l;       /* host [nshell], 0..3 (s, p, d, f; cartesian) */
+    const double *shell_exp;      /* host [nshell], Gaussian exponent alpha > 0 */
+} occrik_basis;
+
+typedef struct {
+    int32_t kmesh[3];             /* M_1, M_2, M_3 >= 1 */
+    int32_t grid[3];              /* N_1, N_2, N_3, each in the supported set */
+    int32_t nocc;                 /* occupied orbitals per k, 1..16 */
+    int32_t kernel;               /* OCCRIK_KERNEL_* */
+    double omega;                 /* range-separation parameter (bohr^-1) for ERF_LR / ERFC_SR */
+    int32_t nyquist;              /* OCCRIK_NYQUIST_* */
+    int32_t precision;            /* OCCRIK_PREC_* */
+    double lattice_tol;           /* lattice-sum truncation, e.g. 1e-12; must be in (0, 1e-3] */
+    int32_t kbatch;               /* summed k-points per FFT batch; 0 = chosen by the plan */
+    int32_t flags;                /* reserved, must be 0 */
+    size_t mem_budget;            /* device bytes the plan may allocate; 0 = no limit */
+} occrik_params;
+
+typedef struct occrik_plan occrik_plan;
+
+typedef struct {
+    int32_t nk, nao, nocc, ng;
+    int32_t grid[3], kmesh[3];
+    int32_t precision, nyquist, kernel, kbatch;
+    double omega, cell_volume;
+    size_t bytes_chi;             /* Bloch AOs on the grid */
+    size_t bytes_workspace;       /* everything else the plan allocated */
+    int64_t pair_transforms;      /* forward+inverse 3D FFT pairs per build */
+    double plan_seconds;          /* wall time of occrik_plan_create */
+} occrik_plan_info;
+
+/* Per-phase device timings of the last build(s), from HIP events recorded on
+ * the plan's stream when profiling is enabled (occrik_set_profiling).  The
+ * pair phase is the fused FFT round trip (the paper's bottleneck, Sec. II.D). */
+typedef struct {
+    double ms_orbitals;           /* psi = chi C (eq. occmo) */
+    double ms_pairs;              /* all FFT passes + W accumulation (Alg. 3 inner loops) */
+    double ms_contract;           /* K_{mu j} contraction */
+    double ms_assemble;           /* K_ij, Cholesky, K~, E_x */
+    int64_t launches_pairs;       /* kernel launches inside ms_pairs */
+    int64_t builds;               /* builds accumulated since the last reset */
+} occrik_profile;
+
+/* Create a plan: validates the inputs, derives the reciprocal lattice and the
+ * per-shell image lists, allocates the device workspaces and collocates the
+ * Bloch AOs on the grid (stored for every build, as the paper assumes in
+ * Sec. II.A).  device: HIP ordinal; stream: a hipStream_t or NULL for the
+ * default stream.  *out is NULL on failure. */
+occrik_status occrik_plan_create(const occrik_cell *cell, const occrik_basis *basis,
+                                 const occrik_params *params, int device, void *stream,
+                                 occrik_plan **out);
+
+/* Free every device and host resource of a plan (NULL is ignored). */
+void occrik_plan_destroy(occrik_plan *plan);
+
+occrik_status occrik_plan_query(const occrik_plan *plan, occrik_plan_info *info);
+
+/* Rebind the plan to another stream of the same device (NULL = default stream). */
+occrik_status occrik_set_stream(occrik_plan *plan, void *stream);
+
+/* Change omega for later builds (kernels ERF_LR / ERFC_SR); omega > 0. */
+occrik_status occrik_set_omega(occrik_plan *plan, double omega);
+
+/* Synchronous build from host memory.
+ *   C   [N_k][N_ao][nocc] complex128 (input)
+ *   K   [N_k][N_ao][N_ao] complex128 (output K~) or NULL
+ *   Kmi [N_k][N_ao][nocc] complex128 (output K_{mu j}) or NULL
+ *   Ex  one double (output E_x) or NULL
+ * Returns OCCRIK_ERR_NONFINITE for NaN/Inf in C (checked on the host before any
+ * device work) and OCCRIK_ERR_NOT_PD when -K_ij(k) has no Cholesky factor. */
+occrik_status occrik_build(occrik_plan *plan, const double *C, double *K, double *Kmi, double *Ex);
+
+/* Asynchronous build from device memory, enqueued on the plan's stream.
+ * dC, dK, dKmi as above but device pointers (dK / dKmi may be NULL); dEx is a
+ * device pointer to one double or NULL.  Launch errors are returned at once;
+ * conditions found on the device (NaN/Inf in C, a failed Cholesky) are
+ * reported by occrik_plan_status after the stream reaches them.  If dK is
+ * non-NULL and a Cholesky fails, the K~ block of that k is left zeroed. */
+occrik_status occrik_build_device(occrik_plan *plan, const void *dC, void *dK, void *dKmi, double *dEx);
+
+/* Synchronise the plan's stream and return the deferred device status of the
+ * last build (OCCRIK_OK, OCCRIK_ERR_NOT_PD or OCCRIK_ERR_NONFINITE). */
+occrik_status occrik_plan_status(occrik_plan *plan);
+
+/* k index of the last OCCRIK_ERR_NOT_PD, or -1. */
+int32_t occrik_last_error_k(const occrik_plan *plan);
+
+/* Gradients of E_x after a build on this plan (not part of the paper; the
+ * adjoint of the build).  With gEx = dL/dE_x:
+ *   dgradC     [N_k][N_ao][nocc] complex128 device buffer (or NULL) receives
+ *              gEx * (2/N_k) K_{mu j}, i.e. dL/dRe C + i dL/dIm C.  This is the
+ *              exact gradient for OCCRIK_NYQUIST_SYMMETRIC; with FFTFREQ it
+ *              differs by a Nyquist-plane term.
+ *   dgradOmega host double (or NULL) receives gEx * dE_x/domega,
+ *              dE_x/domega = -(Omega / 2 N_k^2 N_g^2) sum_{pairs, G} df/domega |u^(G)|^2,
+ *              from a forward-FFT-only sweep over the pair densities (the
+ *              potentials are recomputed, never stored).  Synchronous.
+ * Enqueued on the plan's stream; returns OCCRIK_ERR_STATE before a build. */
+occrik_status occrik_grad(occrik_plan *plan, double gEx, void *dgradC, double *dgradOmega);
+
+/* Ragged batch: n independent plans (different cells, bases, meshes, grids,
+ * nocc) built back to back with their device buffers; per-plan arguments as in
+ * occrik_build_device.  All plans must share one device and one stream. */
+occrik_status occrik_build_batch(int32_t n, occrik_plan *const *plans, const void *const *dC,
+                                 void *const *dK, void *const *dKmi, double *const *dEx);
+
+/* Profiling: when on, every build records HIP events around its phases on the
+ * plan's stream; occrik_get_profile synchronises and returns the accumulated
+ * milliseconds since the last reset (reset = 1 clears them afterwards). */
+occrik_status occrik_set_profiling(occrik_plan *plan, int32_t on);
+occrik_status occrik_get_profile(occrik_plan *plan, occrik_profile *out, int32_t reset);
+
+/* Diagnostics: copy a plan-owned intermediate into caller device memory,
+ * converted to complex128, row-major.
+ *   which = 0: chi~ [N_k][N_ao][N_g], the cell-periodic Bloch AOs e^{-ik.r} chi_{mu k}(r)
+ *   which = 1: psi~ [N_k][nocc][N_g], e^{-ik.r} psi_{i k}(r) of the last build
+ *   which = 2: W~   [N_k][nocc][N_g], e^{-ik.r} W_{j k}(r) of the last build
+ * bytes must equal the size of that array in complex128. */
+occrik_status occrik_copy_intermediate(occrik_plan *plan, int32_t which, void *dst, size_t bytes);
+
+const char *occrik_status_string(occrik_status s);
+const char *occrik_last_error_message(void);
+
+/* 1 if the grid size n is supported along one dimension, else 0. */
+int32_t occrik_grid_size_supported(int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCCRIK_H */

@@ -1,0 +1,260 @@
+// Batched 1D FFTs of a 2D tile held in LDS (self-sorting mixed-radix Stockham).
+//
+// A tile of `lines` lines of length N sits in LDS; element e of line l is at
+// buf[l * ls + e * es].  Every stage reads each point once into registers,
+// synchronises the workgroup, applies twiddles and a radix-R DFT in registers
+// and writes each point once, so one LDS buffer suffices.  The transform is
+// unnormalised: DIR = -1 computes X_m = sum_n x_n e^{-2 pi i m n / N}, DIR = +1
+// the same with e^{+...}.  Output is in natural order.
+//
+// Twiddles come from an LDS table tw[t] = e^{-2 pi i t / N}, t in [0, N),
+// computed in FP64 on the host and rounded once to the working precision.
+#pragma once
+
+#include "common.hpp"
+
+namespace occrik {
+
+// ---------------------------------------------------------------------------
+// in-register DFTs of size R (R in {2, 3, 4, 5, 6, 8})
+// ---------------------------------------------------------------------------
+template <typename T, int R, int DIR> struct Dft;
+
+template <typename T, int DIR> struct Dft<T, 2, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        cplx<T> a = v[0], b = v[1];
+        v[0] = cadd<T>(a, b);
+        v[1] = csub<T>(a, b);
+    }
+};
+
+template <typename T, int DIR> struct Dft<T, 3, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        const T c = T(-0.5);
+        const T s = T(0.86602540378443864676372317075294);
+        cplx<T> t = cadd<T>(v[1], v[2]);
+        cplx<T> u = csub<T>(v[1], v[2]);
+        cplx<T> x0 = v[0];
+        cplx<T> m = mk<T>(x0.x + c * t.x, x0.y + c * t.y);
+        cplx<T> su = mul_i<T, DIR>(cscale<T>(u, s));     // DIR * i * s * u
+        v[0] = cadd<T>(x0, t);
+        v[1] = cadd<T>(m, su);
+        v[2] = csub<T>(m, su);
+    }
+};
+
+template <typename T, int DIR> struct Dft<T, 4, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        cplx<T> a = cadd<T>(v[0], v[2]);
+        cplx<T> b = csub<T>(v[0], v[2]);
+        cplx<T> c = cadd<T>(v[1], v[3]);
+        cplx<T> d = mul_i<T, DIR>(csub<T>(v[1], v[3]));
+        v[0] = cadd<T>(a, c);
+        v[2] = csub<T>(a, c);
+        v[1] = cadd<T>(b, d);
+        v[3] = csub<T>(b, d);
+    }
+};
+
+template <typename T, int DIR> struct Dft<T, 5, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        const T c1 = T(0.30901699437494742410229341718282);    // cos(2 pi / 5)
+        const T c2 = T(-0.80901699437494742410229341718282);   // cos(4 pi / 5)
+        const T s1 = T(0.95105651629515357211643933337938);    // sin(2 pi / 5)
+        const T s2 = T(0.58778525229247312916870595463907);    // sin(4 pi / 5)
+        cplx<T> x0 = v[0];
+        cplx<T> t1 = cadd<T>(v[1], v[4]), u1 = csub<T>(v[1], v[4]);
+        cplx<T> t2 = cadd<T>(v[2], v[3]), u2 = csub<T>(v[2], v[3]);
+        cplx<T> a1 = mk<T>(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+        cplx<T> a2 = mk<T>(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+        cplx<T> b1 = mul_i<T, DIR>(mk<T>(s1 * u1.x + s2 * u2.x, s1 * u1.y + s2 * u2.y));
+        cplx<T> b2 = mul_i<T, DIR>(mk<T>(s2 * u1.x - s1 * u2.x, s2 * u1.y - s1 * u2.y));
+        v[0] = mk<T>(x0.x + t1.x + t2.x, x0.y + t1.y + t2.y);
+        v[1] = cadd<T>(a1, b1);
+        v[4] = csub<T>(a1, b1);
+        v[2] = cadd<T>(a2, b2);
+        v[3] = csub<T>(a2, b2);
+    }
+};
+
+// 6 = 3 x 2: inner 3-point DFTs over x[2 n1 + n2], twiddle w6^{n2 k1}, outer 2-point.
+template <typename T, int DIR> struct Dft<T, 6, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        cplx<T> e[3] = {v[0], v[2], v[4]};
+        cplx<T> o[3] = {v[1], v[3], v[5]};
+        Dft<T, 3, DIR>::run(e);
+        Dft<T, 3, DIR>::run(o);
+        const T h = T(0.5), s = T(0.86602540378443864676372317075294);
+        // w6^1 = (1/2, DIR*s), w6^2 = (-1/2, DIR*s)
+        o[1] = cmul<T>(o[1], mk<T>(h, T(DIR) * s));
+        o[2] = cmul<T>(o[2], mk<T>(-h, T(DIR) * s));
+        v[0] = cadd<T>(e[0], o[0]);
+        v[3] = csub<T>(e[0], o[0]);
+        v[1] = cadd<T>(e[1], o[1]);
+        v[4] = csub<T>(e[1], o[1]);
+        v[2] = cadd<T>(e[2], o[2]);
+        v[5] = csub<T>(e[2], o[2]);
+    }
+};
+
+// 8 = 2 x 4: inner 2-point DFTs over (x[n2], x[n2 + 4]), twiddle w8^{n2 k1}, outer 4-point.
+template <typename T, int DIR> struct Dft<T, 8, DIR> {
+    static __device__ inline void run(cplx<T>* v) {
+        cplx<T> y0[4], y1[4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            y0[n2] = cadd<T>(v[n2], v[n2 + 4]);
+            y1[n2] = csub<T>(v[n2], v[n2 + 4]);
+        }
+        const T r = T(0.70710678118654752440084436210485);
+        // w8^1 = r(1, DIR), w8^2 = DIR i, w8^3 = r(-1, DIR)
+        y1[1] = mk<T>(r * (y1[1].x - T(DIR) * y1[1].y), r * (y1[1].y + T(DIR) * y1[1].x));
+        y1[2] = mul_i<T, DIR>(y1[2]);
+        y1[3] = mk<T>(r * (-y1[3].x - T(DIR) * y1[3].y), r * (-y1[3].y + T(DIR) * y1[3].x));
+        Dft<T, 4, DIR>::run(y0);
+        Dft<T, 4, DIR>::run(y1);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            v[2 * k2] = y0[k2];
+            v[2 * k2 + 1] = y1[k2];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// radix schedules of the supported lengths
+// ---------------------------------------------------------------------------
+template <int N> struct Sched;
+#define OCCRIK_SCHED(N_, a_, b_, c_)                                   \
+    template <> struct Sched<N_> {                                     \
+        static constexpr int r0 = a_, r1 = b_, r2 = c_;                \
+    };
+OCCRIK_SCHED(2, 2, 0, 0)
+OCCRIK_SCHED(3, 3, 0, 0)
+OCCRIK_SCHED(4, 4, 0, 0)
+OCCRIK_SCHED(5, 5, 0, 0)
+OCCRIK_SCHED(6, 6, 0, 0)
+OCCRIK_SCHED(8, 8, 0, 0)
+OCCRIK_SCHED(9, 3, 3, 0)
+OCCRIK_SCHED(10, 5, 2, 0)
+OCCRIK_SCHED(12, 4, 3, 0)
+OCCRIK_SCHED(15, 5, 3, 0)
+OCCRIK_SCHED(16, 4, 4, 0)
+OCCRIK_SCHED(18, 6, 3, 0)
+OCCRIK_SCHED(20, 5, 4, 0)
+OCCRIK_SCHED(24, 8, 3, 0)
+OCCRIK_SCHED(25, 5, 5, 0)
+OCCRIK_SCHED(27, 3, 3, 3)
+OCCRIK_SCHED(30, 6, 5, 0)
+OCCRIK_SCHED(32, 8, 4, 0)
+OCCRIK_SCHED(36, 6, 6, 0)
+OCCRIK_SCHED(40, 8, 5, 0)
+OCCRIK_SCHED(45, 5, 3, 3)
+OCCRIK_SCHED(48, 8, 6, 0)
+OCCRIK_SCHED(50, 5, 5, 2)
+OCCRIK_SCHED(54, 6, 3, 3)
+OCCRIK_SCHED(60, 6, 5, 2)
+OCCRIK_SCHED(64, 8, 8, 0)
+#undef OCCRIK_SCHED
+
+// The supported lengths, for host-side validation (1 means "no transform").
+inline bool grid_size_supported(int n) {
+    switch (n) {
+        case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 9: case 10: case 12:
+        case 15: case 16: case 18: case 20: case 24: case 25: case 27: case 30: case 32:
+        case 36: case 40: case 45: case 48: case 50: case 54: case 60: case 64:
+            return true;
+        default:
+            return false;
+    }
+}
+
+// One Stockham stage of radix R after sub-transforms of length NS.
+template <typename T, int N, int R, int NS, int DIR>
+__device__ inline void stockham_stage(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+    constexpr int NB = N / R;                                   // butterflies per line
+    constexpr int ITEMS = (kMaxN * NB + kFftThreads - 1) / kFftThreads;
+    constexpr int TWS = N / (NS * R);                           // twiddle index step
+    cplx<T> v[ITEMS][R];
+    const int total = lines * NB;
+#pragma unroll
+    for (int t = 0; t < ITEMS; ++t) {
+        const int it = threadIdx.x + t * kFftThreads;
+        if (it < total) {
+            const int line = it / NB;
+            const int j = it - line * NB;
+            const cplx<T>* p = buf + line * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[t][r] = p[(j + r * NB) * es];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < ITEMS; ++t) {
+        const int it = threadIdx.x + t * kFftThreads;
+        if (it < total) {
+            const int line = it / NB;
+            const int j = it - line * NB;
+            const int jm = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cplx<T> w = tw[jm * r * TWS];
+                    if (DIR > 0) w.y = -w.y;
+                    v[t][r] = cmul<T>(v[t][r], w);
+                }
+            }
+            Dft<T, R, DIR>::run(v[t]);
+            const int base = (j / NS) * NS * R + jm;
+            cplx<T>* p = buf + line * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[(base + r * NS) * es] = v[t][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of length N along every line of the tile.  The caller must
+// have synchronised after writing the tile; the tile is ready on return.
+template <typename T, int N, int DIR>
+__device__ inline void fft_lines(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+    using S = Sched<N>;
+    stockham_stage<T, N, S::r0, 1, DIR>(buf, lines, es, ls, tw);
+    if constexpr (S::r1 != 0) stockham_stage<T, N, S::r1, S::r0, DIR>(buf, lines, es, ls, tw);
+    if constexpr (S::r2 != 0) stockham_stage<T, N, S::r2, S::r0 * S::r1, DIR>(buf, lines, es, ls, tw);
+}
+
+template <typename T, int DIR>
+__device__ inline void fft_lines_n(int n, cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+    switch (n) {
+        case 2: fft_lines<T, 2, DIR>(buf, lines, es, ls, tw); break;
+        case 3: fft_lines<T, 3, DIR>(buf, lines, es, ls, tw); break;
+        case 4: fft_lines<T, 4, DIR>(buf, lines, es, ls, tw); break;
+        case 5: fft_lines<T, 5, DIR>(buf, lines, es, ls, tw); break;
+        case 6: fft_lines<T, 6, DIR>(buf, lines, es, ls, tw); break;
+        case 8: fft_lines<T, 8, DIR>(buf, lines, es, ls, tw); break;
+        case 9: fft_lines<T, 9, DIR>(buf, lines, es, ls, tw); break;
+        case 10: fft_lines<T, 10, DIR>(buf, lines, es, ls, tw); break;
+        case 12: fft_lines<T, 12, DIR>(buf, lines, es, ls, tw); break;
+        case 15: fft_lines<T, 15, DIR>(buf, lines, es, ls, tw); break;
+        case 16: fft_lines<T, 16, DIR>(buf, lines, es, ls, tw); break;
+        case 18: fft_lines<T, 18, DIR>(buf, lines, es, ls, tw); break;
+        case 20: fft_lines<T, 20, DIR>(buf, lines, es, ls, tw); break;
+        case 24: fft_lines<T, 24, DIR>(buf, lines, es, ls, tw); break;
+        case 25: fft_lines<T, 25, DIR>(buf, lines, es, ls, tw); break;
+        case 27: fft_lines<T, 27, DIR>(buf, lines, es, ls, tw); break;
+        case 30: fft_lines<T, 30, DIR>(buf, lines, es, ls, tw); break;
+        case 32: fft_lines<T, 32, DIR>(buf, lines, es, ls, tw); break;
+        case 36: fft_lines<T, 36, DIR>(buf, lines, es, ls, tw); break;
+        case 40: fft_lines<T, 40, DIR>(buf, lines, es, ls, tw); break;
+        case 45: fft_lines<T, 45, DIR>(buf, lines, es, ls, tw); break;
+        case 48: fft_lines<T, 48, DIR>(buf, lines, es, ls, tw); break;
+        case 50: fft_lines<T, 50, DIR>(buf, lines, es, ls, tw); break;
+        case 54: fft_lines<T, 54, DIR>(buf, lines, es, ls, tw); break;
+        case 60: fft_lines<T, 60, DIR>(buf, lines, es, ls, tw); break;
+        case 64: fft_lines<T, 64, DIR>(buf, lines, es, ls, tw); break;
+        default: break;                                   // n == 1: identity
+    }
+}
+
+}  // namespace occrik

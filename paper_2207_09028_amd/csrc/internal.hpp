@@ -1,0 +1,95 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/occrik.h"
+#include "common.hpp"
+
+namespace occrik {
+
+// Geometry of one batch of pair round trips: output k-point a, summed k-points
+// b in [b0, b0 + nb), all nocc x nocc orbital pairs.  Pair p of the batch is
+// ((b - b0) * nocc + i) * nocc + j: i the summed orbital at b, j the output
+// orbital at a.  Its density is conj(psi~_{i b}) psi~_{j a}, momentum q = k_a - k_b.
+struct PairBatch {
+    int N1, N2, N3, ng;
+    int M1, M2, M3;
+    int nocc;
+    int a, b0, nb;
+    int kernel, nyquist;
+    double omega;
+    double inv_ng;
+    double recip[9];          // reciprocal vectors b_1, b_2, b_3 (rows)
+    int splits;               // pass-3 splits of the (b, i) sum
+    int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
+};
+
+// Launchers (templated on the working real type: float or double).
+template <typename T>
+hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
+                        hipStream_t s);
+template <typename T>
+hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, const cplx<T>* tw,
+                        hipStream_t s);
+template <typename T>
+hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill_zero(cplx<T>* p, size_t n, hipStream_t s);
+hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s);
+
+template <typename T>
+hipError_t launch_orbitals(const cplx<T>* chi, const double2* C, cplx<T>* psi, int nk, int nao, int nocc, int ng,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart, double2* Kmi, int nk, int nao,
+                           int nocc, int ng, int nchunks, double scale, hipStream_t s);
+
+// Assembly (FP64).
+hipError_t launch_check_finite(const double2* C, size_t n, int* flags, hipStream_t s);
+hipError_t launch_reset_flags_n(int* flags, int n, hipStream_t s);
+hipError_t launch_kij(const double2* C, const double2* Kmi, double2* Kij, double2* L, double* eterm, int* flags,
+                      int nk, int nao, int nocc, hipStream_t s);
+hipError_t launch_xi(const double2* Kmi, const double2* L, double2* Y, const int* flags, int nk, int nao, int nocc,
+                     hipStream_t s);
+hipError_t launch_ktilde(const double2* Y, double2* K, const int* flags, int nk, int nao, int nocc, hipStream_t s);
+hipError_t launch_energy(const double* eterm, int nk, double* out, hipStream_t s);
+hipError_t launch_sum_f64(const double* parts, size_t n, double scale, double* out, hipStream_t s);
+hipError_t launch_scale_copy(const double2* src, double2* dst, size_t n, double scale, hipStream_t s);
+
+// Collocation (plan time).
+struct CollocGeom {
+    double lat[9];            // rows a_1, a_2, a_3
+    int N[3];                 // grid
+    int M[3];                 // k-mesh
+    int nk, ng;
+};
+struct ShellDev {
+    double R[3];
+    double alpha;
+    int l;
+    int ncomp;
+    double norm[10];
+};
+hipError_t launch_colloc_fold(double* phi, const double4* img, const int* bucket, const ShellDev& sh,
+                              const CollocGeom& g, hipStream_t s);
+// Bloch-phase DFT over the image cells of one component: phi_real [L][n] ->
+// result [k][n] (complex128) = sum_L e^{ik.L} phi[L][n].  Uses work0/work1 as
+// ping-pong buffers and returns the one holding the result.
+hipError_t launch_colloc_kdft(const double* phi_real, double2* work0, double2* work1, const CollocGeom& g,
+                              hipStream_t s, double2** result);
+template <typename T>
+hipError_t launch_colloc_store(const double2* chik, cplx<T>* chi, int mu, int nao, const CollocGeom& g, hipStream_t s);
+
+template <typename T>
+hipError_t launch_convert_to_c128(const cplx<T>* src, double2* dst, size_t n, hipStream_t s);
+
+}  // namespace occrik

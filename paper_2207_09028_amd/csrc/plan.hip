@@ -1,0 +1,772 @@
+// Plans and the C ABI of the occ-RI-K library.
+//
+// A plan fixes the cell, basis, k-mesh, grid and kernel, collocates the Bloch
+// AOs on the grid once (the stored-AO variant of the paper's Sec. II.A/II.D)
+// and owns every device workspace of a build:
+//
+//   build = orbitals (eq. occmo) -> pair round trips over all (k, k') blocks
+//           (Alg. 3 loops, batched over the summed k-points) -> contraction ->
+//           FP64 occupied block, Cholesky, assembly and energy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+using namespace occrik;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+occrik_status fail(occrik_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+occrik_status hip_fail(hipError_t e, const char* where) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(OCCRIK_ERR_OOM, std::string(where) + ": " + hipGetErrorString(e));
+    return fail(OCCRIK_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define OCCRIK_HIP(call)                                      \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+struct ProfileEvents {
+    hipEvent_t e[5];
+    int64_t pair_launches;
+};
+
+}  // namespace
+
+struct occrik_plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    occrik_params params{};
+    double lat[9]{}, recip[9]{}, volume = 0.0, dv = 0.0;
+    int N[3]{}, M[3]{};
+    int nk = 0, ng = 0, nao = 0, nocc = 0, natm = 0;
+    std::vector<double> atom_cart;
+    std::vector<int> shell_atom, shell_l;
+    std::vector<double> shell_exp;
+    bool fp64 = true;
+    size_t elem = 16;
+    int kbatch = 1, splits = 1, nchunks = 1;
+
+    // device memory
+    std::vector<void*> allocations;
+    std::vector<size_t> sizes;
+    size_t bytes_alloc = 0, bytes_chi = 0;
+    void* chi = nullptr;       // [nk][nao][ng] cplx<T>
+    void* psi = nullptr;       // [nk][nocc][ng]
+    void* W = nullptr;         // [nk][nocc][ng]
+    void* X = nullptr;         // [kbatch * nocc^2][ng]
+    void* Wpart = nullptr;     // [splits][nocc][ng]
+    void* tw = nullptr;        // [3][kMaxN]
+    double* parts = nullptr;   // [kbatch * nocc^2 * N2]
+    double2* Kpart = nullptr;  // [nk][nao][nocc][nchunks]
+    double2* Kmi = nullptr;    // [nk][nao][nocc]
+    double2* Kij = nullptr;    // [nk][nocc][nocc]
+    double2* L = nullptr;      // [nk][nocc][nocc]
+    double2* Y = nullptr;      // [nk][nao][nocc]
+    double* eterm = nullptr;   // [nk]
+    double* scal = nullptr;    // [4] device scalars
+    int* flags = nullptr;      // [2 + nk]
+
+    bool built = false;
+    int last_err_k = -1;
+    double plan_seconds = 0.0;
+
+    bool profiling = false;
+    std::vector<ProfileEvents> prof;
+    occrik_profile prof_acc{};
+
+    ~occrik_plan() {
+        for (auto& p : prof)
+            for (auto& e : p.e) (void)hipEventDestroy(e);
+        for (void* p : allocations) (void)hipFree(p);
+    }
+
+    hipError_t alloc(void** p, size_t bytes) {
+        if (params.mem_budget != 0 && bytes_alloc + bytes > params.mem_budget) return hipErrorOutOfMemory;
+        hipError_t e = hipMalloc(p, bytes == 0 ? 16 : bytes);
+        if (e == hipSuccess) {
+            allocations.push_back(*p);
+            sizes.push_back(bytes);
+            bytes_alloc += bytes;
+        }
+        return e;
+    }
+    void release(void* p) {
+        for (size_t i = 0; i < allocations.size(); ++i) {
+            if (allocations[i] == p) {
+                (void)hipFree(p);
+                bytes_alloc -= sizes[i];
+                allocations.erase(allocations.begin() + i);
+                sizes.erase(sizes.begin() + i);
+                return;
+            }
+        }
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// geometry helpers (host)
+// ---------------------------------------------------------------------------
+bool invert3(const double* a, double* inv) {
+    const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                       a[2] * (a[3] * a[7] - a[4] * a[6]);
+    if (!(std::fabs(det) > 1e-12) || !std::isfinite(det)) return false;
+    const double id = 1.0 / det;
+    inv[0] = (a[4] * a[8] - a[5] * a[7]) * id;
+    inv[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    inv[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    inv[3] = (a[5] * a[6] - a[3] * a[8]) * id;
+    inv[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    inv[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    inv[6] = (a[3] * a[7] - a[4] * a[6]) * id;
+    inv[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    inv[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+    return true;
+}
+
+double dfact(int n) {
+    double r = 1.0;
+    while (n > 1) {
+        r *= n;
+        n -= 2;
+    }
+    return r;
+}
+
+// radius beyond which N_s r^l exp(-alpha r^2) < tol, N_s the largest component norm
+double shell_extent(double alpha, int l, double tol) {
+    const double ln_n = 0.75 * std::log(2.0 * alpha / M_PI) + 0.5 * l * std::log(4.0 * alpha);
+    const double ln_tol = std::log(tol);
+    auto g = [&](double r) { return ln_n + (l > 0 ? l * std::log(r) : 0.0) - alpha * r * r - ln_tol; };
+    double lo = l > 0 ? std::sqrt(l / (2.0 * alpha)) : 0.0;
+    if (l > 0 && g(lo) < 0.0) return 0.0;
+    if (l == 0 && ln_n - ln_tol < 0.0) return 0.0;
+    double hi = std::max(lo, 1.0);
+    while (g(hi) > 0.0) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (g(mid) > 0.0) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
+int pmod(long a, int m) {
+    long r = a % m;
+    return (int)(r < 0 ? r + m : r);
+}
+
+template <typename T>
+occrik_status run_collocation(occrik_plan* P) {
+    hipStream_t s = P->stream;
+    const int nk = P->nk, ng = P->ng;
+    // cell centre and circumradius
+    double c[3], rho = 0.0;
+    for (int d = 0; d < 3; ++d) c[d] = 0.5 * (P->lat[d] + P->lat[3 + d] + P->lat[6 + d]);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                double q = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double x = i * P->lat[d] + j * P->lat[3 + d] + k * P->lat[6 + d] - c[d];
+                    q += x * x;
+                }
+                rho = std::max(rho, std::sqrt(q));
+            }
+    double inv[9];
+    invert3(P->lat, inv);
+    const int nshell = (int)P->shell_l.size();
+    int maxcomp = 1;
+    for (int l : P->shell_l) maxcomp = std::max(maxcomp, (l + 1) * (l + 2) / 2);
+
+    CollocGeom g{};
+    std::memcpy(g.lat, P->lat, sizeof(g.lat));
+    for (int d = 0; d < 3; ++d) {
+        g.N[d] = P->N[d];
+        g.M[d] = P->M[d];
+    }
+    g.nk = nk;
+    g.ng = ng;
+
+    double* phi = nullptr;
+    double2 *w0 = nullptr, *w1 = nullptr;
+    double4* dimg = nullptr;
+    int* dbucket = nullptr;
+    OCCRIK_HIP(P->alloc((void**)&phi, sizeof(double) * maxcomp * (size_t)nk * ng));
+    OCCRIK_HIP(P->alloc((void**)&w0, sizeof(double2) * (size_t)nk * ng));
+    OCCRIK_HIP(P->alloc((void**)&w1, sizeof(double2) * (size_t)nk * ng));
+    OCCRIK_HIP(P->alloc((void**)&dbucket, sizeof(int) * (nk + 1)));
+    size_t img_cap = 0;
+
+    int mu0 = 0;
+    for (int sh = 0; sh < nshell; ++sh) {
+        const int l = P->shell_l[sh];
+        const double alpha = P->shell_exp[sh];
+        const double* R = &P->atom_cart[3 * P->shell_atom[sh]];
+        const double rs = shell_extent(alpha, l, P->params.lattice_tol);
+        const double reach = rho + rs;
+        double rc = 0.0;
+        for (int d = 0; d < 3; ++d) rc += (R[d] - c[d]) * (R[d] - c[d]);
+        const double bound = reach + std::sqrt(rc);
+        int nmax[3];
+        for (int d = 0; d < 3; ++d) {
+            const double cn = std::sqrt(inv[d] * inv[d] + inv[3 + d] * inv[3 + d] + inv[6 + d] * inv[6 + d]);
+            nmax[d] = (int)std::ceil(bound * cn) + 1;
+        }
+        std::vector<std::vector<double4>> buckets(nk);
+        for (int t1 = -nmax[0]; t1 <= nmax[0]; ++t1)
+            for (int t2 = -nmax[1]; t2 <= nmax[1]; ++t2)
+                for (int t3 = -nmax[2]; t3 <= nmax[2]; ++t3) {
+                    double tv[3], q = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        tv[d] = t1 * P->lat[d] + t2 * P->lat[3 + d] + t3 * P->lat[6 + d];
+                        const double x = R[d] + tv[d] - c[d];
+                        q += x * x;
+                    }
+                    if (q > reach * reach) continue;
+                    const int L = (pmod(t1, P->M[0]) * P->M[1] + pmod(t2, P->M[1])) * P->M[2] + pmod(t3, P->M[2]);
+                    buckets[L].push_back(make_double4(tv[0], tv[1], tv[2], 0.0));
+                }
+        std::vector<double4> flat;
+        std::vector<int> off(nk + 1, 0);
+        for (int L = 0; L < nk; ++L) {
+            off[L] = (int)flat.size();
+            flat.insert(flat.end(), buckets[L].begin(), buckets[L].end());
+        }
+        off[nk] = (int)flat.size();
+        if (flat.size() > img_cap) {
+            OCCRIK_HIP(hipStreamSynchronize(s));
+            if (dimg) P->release(dimg);
+            img_cap = std::max<size_t>(flat.size(), 1024);
+            OCCRIK_HIP(P->alloc((void**)&dimg, sizeof(double4) * img_cap));
+        }
+        // previous shell's kernels may still read the image buffers
+        OCCRIK_HIP(hipStreamSynchronize(s));
+        if (!flat.empty())
+            OCCRIK_HIP(hipMemcpy(dimg, flat.data(), sizeof(double4) * flat.size(), hipMemcpyHostToDevice));
+        OCCRIK_HIP(hipMemcpy(dbucket, off.data(), sizeof(int) * (nk + 1), hipMemcpyHostToDevice));
+
+        ShellDev sd{};
+        for (int d = 0; d < 3; ++d) sd.R[d] = R[d];
+        sd.alpha = alpha;
+        sd.l = l;
+        sd.ncomp = (l + 1) * (l + 2) / 2;
+        int ic = 0;
+        for (int a = l; a >= 0; --a)
+            for (int b = l - a; b >= 0; --b) {
+                const int cz = l - a - b;
+                sd.norm[ic++] = std::pow(2.0 * alpha / M_PI, 0.75) * std::pow(4.0 * alpha, 0.5 * l) /
+                                std::sqrt(dfact(2 * a - 1) * dfact(2 * b - 1) * dfact(2 * cz - 1));
+            }
+        OCCRIK_HIP(launch_colloc_fold(phi, dimg, dbucket, sd, g, s));
+        for (int cc = 0; cc < sd.ncomp; ++cc) {
+            double2* res = nullptr;
+            OCCRIK_HIP(launch_colloc_kdft(phi + (size_t)cc * nk * ng, w0, w1, g, s, &res));
+            OCCRIK_HIP(launch_colloc_store<T>(res, reinterpret_cast<cplx<T>*>(P->chi), mu0 + cc, P->nao, g, s));
+        }
+        mu0 += sd.ncomp;
+    }
+    OCCRIK_HIP(hipStreamSynchronize(s));
+    P->release(phi);
+    P->release(w0);
+    P->release(w1);
+    P->release(dimg);
+    P->release(dbucket);
+    return OCCRIK_OK;
+}
+
+template <typename T>
+occrik_status make_twiddles(occrik_plan* P) {
+    std::vector<cplx<T>> h(3 * kMaxN);
+    for (int d = 0; d < 3; ++d)
+        for (int t = 0; t < kMaxN; ++t) {
+            cplx<T> v;
+            if (t < P->N[d]) {
+                const double a = -2.0 * M_PI * double(t) / double(P->N[d]);
+                v.x = T(std::cos(a));
+                v.y = T(std::sin(a));
+            } else {
+                v.x = T(0);
+                v.y = T(0);
+            }
+            h[d * kMaxN + t] = v;
+        }
+    OCCRIK_HIP(hipMemcpy(P->tw, h.data(), sizeof(cplx<T>) * h.size(), hipMemcpyHostToDevice));
+    return OCCRIK_OK;
+}
+
+PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
+    PairBatch B{};
+    B.N1 = P->N[0];
+    B.N2 = P->N[1];
+    B.N3 = P->N[2];
+    B.ng = P->ng;
+    B.M1 = P->M[0];
+    B.M2 = P->M[1];
+    B.M3 = P->M[2];
+    B.nocc = P->nocc;
+    B.a = a;
+    B.b0 = b0;
+    B.nb = nb;
+    B.kernel = P->params.kernel;
+    B.nyquist = P->params.nyquist;
+    B.omega = P->params.omega;
+    B.inv_ng = 1.0 / P->ng;
+    std::memcpy(B.recip, P->recip, sizeof(B.recip));
+    B.splits = P->splits;
+    B.parseval = 0;
+    return B;
+}
+
+template <typename T>
+occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2* dKmi, double* dEx) {
+    hipStream_t s = P->stream;
+    const int nk = P->nk, nao = P->nao, nocc = P->nocc, ng = P->ng;
+    cplx<T>* chi = reinterpret_cast<cplx<T>*>(P->chi);
+    cplx<T>* psi = reinterpret_cast<cplx<T>*>(P->psi);
+    cplx<T>* W = reinterpret_cast<cplx<T>*>(P->W);
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(P->X);
+    cplx<T>* Wp = reinterpret_cast<cplx<T>*>(P->Wpart);
+    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(P->tw);
+    ProfileEvents pe{};
+    if (P->profiling) {
+        for (auto& e : pe.e) OCCRIK_HIP(hipEventCreate(&e));
+        OCCRIK_HIP(hipEventRecord(pe.e[0], s));
+    }
+    OCCRIK_HIP(launch_reset_flags_n(P->flags, 2 + nk, s));
+    OCCRIK_HIP(launch_check_finite(dC, (size_t)nk * nao * nocc, P->flags, s));
+    OCCRIK_HIP(launch_orbitals<T>(chi, dC, psi, nk, nao, nocc, ng, s));
+    if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
+    OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
+    int64_t launches = 1;
+    for (int a = 0; a < nk; ++a) {
+        for (int b0 = 0; b0 < nk; b0 += P->kbatch) {
+            const int nb = std::min(P->kbatch, nk - b0);
+            PairBatch B = make_batch(P, a, b0, nb);
+            OCCRIK_HIP(launch_pass1<T>(B, psi, X, tw, s));
+            OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 0, s));
+            OCCRIK_HIP(launch_pass3<T>(B, X, psi, Wp, tw, s));
+            OCCRIK_HIP(launch_wreduce<T>(B, Wp, W, s));
+            launches += 4;
+        }
+    }
+    if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[2], s));
+    OCCRIK_HIP(launch_contract<T>(chi, W, P->Kpart, P->Kmi, nk, nao, nocc, ng, P->nchunks, -P->dv / nk, s));
+    if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[3], s));
+    if (dKmi) OCCRIK_HIP(hipMemcpyAsync(dKmi, P->Kmi, sizeof(double2) * nk * nao * nocc, hipMemcpyDeviceToDevice, s));
+    OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, s));
+    if (dK) {
+        OCCRIK_HIP(launch_xi(P->Kmi, P->L, P->Y, P->flags, nk, nao, nocc, s));
+        OCCRIK_HIP(launch_ktilde(P->Y, dK, P->flags, nk, nao, nocc, s));
+    }
+    if (dEx) OCCRIK_HIP(launch_energy(P->eterm, nk, dEx, s));
+    if (P->profiling) {
+        OCCRIK_HIP(hipEventRecord(pe.e[4], s));
+        pe.pair_launches = launches;
+        P->prof.push_back(pe);
+    }
+    P->built = true;
+    return OCCRIK_OK;
+}
+
+template <typename T>
+occrik_status domega_impl(occrik_plan* P, double* out_host) {
+    hipStream_t s = P->stream;
+    const int nk = P->nk;
+    cplx<T>* psi = reinterpret_cast<cplx<T>*>(P->psi);
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(P->X);
+    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(P->tw);
+    OCCRIK_HIP(launch_fill_zero_f64(P->scal, 4, s));
+    const double scale = -P->volume / (2.0 * double(nk) * nk * double(P->ng) * P->ng);
+    for (int a = 0; a < nk; ++a)
+        for (int b0 = 0; b0 < nk; b0 += P->kbatch) {
+            const int nb = std::min(P->kbatch, nk - b0);
+            PairBatch B = make_batch(P, a, b0, nb);
+            OCCRIK_HIP(launch_pass1<T>(B, psi, X, tw, s));
+            OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 1, s));
+            OCCRIK_HIP(launch_sum_f64(P->parts, (size_t)nb * P->nocc * P->nocc * P->N[1], scale, P->scal, s));
+        }
+    OCCRIK_HIP(hipMemcpyAsync(out_host, P->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    OCCRIK_HIP(hipStreamSynchronize(s));
+    return OCCRIK_OK;
+}
+
+occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const occrik_params* pr) {
+    if (!cell || !basis || !pr) return fail(OCCRIK_ERR_INVALID_ARG, "null cell, basis or params");
+    double inv[9];
+    for (double v : cell->lattice)
+        if (!std::isfinite(v)) return fail(OCCRIK_ERR_INVALID_ARG, "non-finite lattice");
+    if (!invert3(cell->lattice, inv)) return fail(OCCRIK_ERR_INVALID_ARG, "singular lattice");
+    if (cell->natm < 1 || !cell->atom_frac) return fail(OCCRIK_ERR_INVALID_ARG, "no atoms");
+    for (int i = 0; i < 3 * cell->natm; ++i)
+        if (!std::isfinite(cell->atom_frac[i])) return fail(OCCRIK_ERR_INVALID_ARG, "non-finite atom position");
+    if (basis->nshell < 1 || !basis->shell_atom || !basis->shell_l || !basis->shell_exp)
+        return fail(OCCRIK_ERR_INVALID_ARG, "empty basis");
+    for (int s = 0; s < basis->nshell; ++s) {
+        if (basis->shell_atom[s] < 0 || basis->shell_atom[s] >= cell->natm)
+            return fail(OCCRIK_ERR_INVALID_ARG, "shell_atom out of range");
+        if (basis->shell_l[s] < 0) return fail(OCCRIK_ERR_INVALID_ARG, "negative shell_l");
+        if (basis->shell_l[s] > 3) return fail(OCCRIK_ERR_UNSUPPORTED, "shell_l > 3");
+        if (!(basis->shell_exp[s] > 0.0) || !std::isfinite(basis->shell_exp[s]))
+            return fail(OCCRIK_ERR_INVALID_ARG, "shell exponent must be positive and finite");
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (pr->kmesh[d] < 1 || pr->kmesh[d] > 16) return fail(OCCRIK_ERR_INVALID_ARG, "kmesh entries must be 1..16");
+        if (pr->grid[d] < 1) return fail(OCCRIK_ERR_INVALID_ARG, "grid entries must be >= 1");
+        if (!grid_size_supported(pr->grid[d]))
+            return fail(OCCRIK_ERR_UNSUPPORTED, "grid size " + std::to_string(pr->grid[d]) + " not supported");
+    }
+    if (pr->nocc < 1 || pr->nocc > 16) return fail(OCCRIK_ERR_INVALID_ARG, "nocc must be 1..16");
+    if (pr->kernel < 0 || pr->kernel > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
+    if (pr->kernel != OCCRIK_KERNEL_COULOMB && !(pr->omega > 0.0 && std::isfinite(pr->omega)))
+        return fail(OCCRIK_ERR_INVALID_ARG, "omega must be positive for range-separated kernels");
+    if (pr->nyquist < 0 || pr->nyquist > 1) return fail(OCCRIK_ERR_INVALID_ARG, "unknown nyquist mode");
+    if (pr->precision < 0 || pr->precision > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown precision");
+    if (!(pr->lattice_tol > 0.0 && pr->lattice_tol <= 1e-3)) return fail(OCCRIK_ERR_INVALID_ARG, "lattice_tol");
+    if (pr->flags != 0) return fail(OCCRIK_ERR_INVALID_ARG, "flags must be 0");
+    if (pr->kbatch < 0) return fail(OCCRIK_ERR_INVALID_ARG, "kbatch must be >= 0");
+    return OCCRIK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* occrik_status_string(occrik_status s) {
+    switch (s) {
+        case OCCRIK_OK: return "OCCRIK_OK";
+        case OCCRIK_ERR_INVALID_ARG: return "OCCRIK_ERR_INVALID_ARG";
+        case OCCRIK_ERR_UNSUPPORTED: return "OCCRIK_ERR_UNSUPPORTED";
+        case OCCRIK_ERR_OOM: return "OCCRIK_ERR_OOM";
+        case OCCRIK_ERR_NOT_PD: return "OCCRIK_ERR_NOT_PD";
+        case OCCRIK_ERR_NONFINITE: return "OCCRIK_ERR_NONFINITE";
+        case OCCRIK_ERR_DEVICE: return "OCCRIK_ERR_DEVICE";
+        case OCCRIK_ERR_STATE: return "OCCRIK_ERR_STATE";
+    }
+    return "OCCRIK_UNKNOWN";
+}
+
+const char* occrik_last_error_message(void) { return g_last_error.c_str(); }
+
+int32_t occrik_grid_size_supported(int32_t n) { return grid_size_supported(n) ? 1 : 0; }
+
+occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* basis, const occrik_params* params,
+                                 int device, void* stream, occrik_plan** out) {
+    if (!out) return fail(OCCRIK_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    occrik_status st = validate(cell, basis, params);
+    if (st != OCCRIK_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(OCCRIK_ERR_DEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(OCCRIK_ERR_INVALID_ARG, "device ordinal out of range");
+    const auto t0 = std::chrono::steady_clock::now();
+    DeviceGuard guard(device);
+    auto* P = new occrik_plan();
+    P->device = device;
+    P->stream = reinterpret_cast<hipStream_t>(stream);
+    P->params = *params;
+    std::memcpy(P->lat, cell->lattice, sizeof(P->lat));
+    double inv[9];
+    invert3(P->lat, inv);
+    // b_d = 2 pi (A^{-1})^T rows: recip[d][e] = 2 pi inv[e][d]
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) P->recip[3 * d + e] = 2.0 * M_PI * inv[3 * e + d];
+    const double det = P->lat[0] * (P->lat[4] * P->lat[8] - P->lat[5] * P->lat[7]) -
+                       P->lat[1] * (P->lat[3] * P->lat[8] - P->lat[5] * P->lat[6]) +
+                       P->lat[2] * (P->lat[3] * P->lat[7] - P->lat[4] * P->lat[6]);
+    P->volume = std::fabs(det);
+    for (int d = 0; d < 3; ++d) {
+        P->N[d] = params->grid[d];
+        P->M[d] = params->kmesh[d];
+    }
+    P->nk = P->M[0] * P->M[1] * P->M[2];
+    P->ng = P->N[0] * P->N[1] * P->N[2];
+    P->dv = P->volume / P->ng;
+    P->natm = cell->natm;
+    P->atom_cart.resize(3 * P->natm);
+    for (int a = 0; a < P->natm; ++a)
+        for (int e = 0; e < 3; ++e) {
+            double x = 0.0;
+            for (int d = 0; d < 3; ++d) x += cell->atom_frac[3 * a + d] * P->lat[3 * d + e];
+            P->atom_cart[3 * a + e] = x;
+        }
+    P->shell_atom.assign(basis->shell_atom, basis->shell_atom + basis->nshell);
+    P->shell_l.assign(basis->shell_l, basis->shell_l + basis->nshell);
+    P->shell_exp.assign(basis->shell_exp, basis->shell_exp + basis->nshell);
+    P->nao = 0;
+    for (int l : P->shell_l) P->nao += (l + 1) * (l + 2) / 2;
+    P->nocc = params->nocc;
+    if (P->nocc > P->nao) {
+        delete P;
+        return fail(OCCRIK_ERR_INVALID_ARG, "nocc exceeds the number of AOs");
+    }
+    P->fp64 = params->precision == OCCRIK_PREC_FP64;
+    P->elem = P->fp64 ? 16 : 8;
+
+    const int nk = P->nk, ng = P->ng, nao = P->nao, nocc = P->nocc;
+    const size_t per_k = (size_t)nocc * nocc * ng * P->elem;
+    if (params->kbatch > 0) {
+        P->kbatch = std::min(params->kbatch, nk);
+    } else {
+        const size_t cap = (size_t)16 << 30;
+        P->kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_k));
+    }
+    const int target_wg = 2048;
+    const int base_wg = P->N[0] * nocc;
+    P->splits = std::max(1, std::min(P->kbatch * nocc, (target_wg + base_wg - 1) / base_wg));
+    P->nchunks = std::max(1, std::min(64, ng / 4096));
+
+    hipError_t e = hipSuccess;
+    auto A = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = P->alloc(p, bytes);
+    };
+    P->bytes_chi = (size_t)nk * nao * ng * P->elem;
+    A(&P->chi, P->bytes_chi);
+    A(&P->psi, (size_t)nk * nocc * ng * P->elem);
+    A(&P->W, (size_t)nk * nocc * ng * P->elem);
+    A(&P->X, (size_t)P->kbatch * per_k);
+    A(&P->Wpart, (size_t)P->splits * nocc * ng * P->elem);
+    A(&P->tw, 3 * kMaxN * P->elem);
+    A((void**)&P->parts, sizeof(double) * (size_t)P->kbatch * nocc * nocc * P->N[1]);
+    A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nocc * P->nchunks);
+    A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nocc);
+    A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nocc * nocc);
+    A((void**)&P->L, sizeof(double2) * (size_t)nk * nocc * nocc);
+    A((void**)&P->Y, sizeof(double2) * (size_t)nk * nao * nocc);
+    A((void**)&P->eterm, sizeof(double) * nk);
+    A((void**)&P->scal, sizeof(double) * 4);
+    A((void**)&P->flags, sizeof(int) * (2 + nk));
+    if (e != hipSuccess) {
+        delete P;
+        return hip_fail(e, "plan allocation");
+    }
+    st = P->fp64 ? make_twiddles<double>(P) : make_twiddles<float>(P);
+    if (st == OCCRIK_OK) st = P->fp64 ? run_collocation<double>(P) : run_collocation<float>(P);
+    if (st != OCCRIK_OK) {
+        delete P;
+        return st;
+    }
+    P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P;
+    return OCCRIK_OK;
+}
+
+void occrik_plan_destroy(occrik_plan* plan) {
+    if (!plan) return;
+    DeviceGuard guard(plan->device);
+    (void)hipStreamSynchronize(plan->stream);
+    delete plan;
+}
+
+occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
+    if (!P || !info) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or info");
+    info->nk = P->nk;
+    info->nao = P->nao;
+    info->nocc = P->nocc;
+    info->ng = P->ng;
+    for (int d = 0; d < 3; ++d) {
+        info->grid[d] = P->N[d];
+        info->kmesh[d] = P->M[d];
+    }
+    info->precision = P->params.precision;
+    info->nyquist = P->params.nyquist;
+    info->kernel = P->params.kernel;
+    info->kbatch = P->kbatch;
+    info->omega = P->params.omega;
+    info->cell_volume = P->volume;
+    info->bytes_chi = P->bytes_chi;
+    info->bytes_workspace = P->bytes_alloc - P->bytes_chi;
+    info->pair_transforms = (int64_t)P->nk * P->nk * P->nocc * P->nocc;
+    info->plan_seconds = P->plan_seconds;
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_set_stream(occrik_plan* P, void* stream) {
+    if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    P->stream = reinterpret_cast<hipStream_t>(stream);
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_set_omega(occrik_plan* P, double omega) {
+    if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(OCCRIK_ERR_INVALID_ARG, "omega must be positive");
+    P->params.omega = omega;
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_build_device(occrik_plan* P, const void* dC, void* dK, void* dKmi, double* dEx) {
+    if (!P || !dC) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C");
+    DeviceGuard guard(P->device);
+    P->last_err_k = -1;
+    return P->fp64 ? build_impl<double>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx)
+                   : build_impl<float>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx);
+}
+
+occrik_status occrik_plan_status(occrik_plan* P) {
+    if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    DeviceGuard guard(P->device);
+    int h[2];
+    OCCRIK_HIP(hipMemcpyAsync(h, P->flags, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+    OCCRIK_HIP(hipStreamSynchronize(P->stream));
+    if (h[0]) return fail(OCCRIK_ERR_NONFINITE, "non-finite entries in C");
+    if (h[1] != INT_MAX) {
+        P->last_err_k = h[1];
+        return fail(OCCRIK_ERR_NOT_PD, "-K_ij is not positive definite at k = " + std::to_string(h[1]));
+    }
+    return OCCRIK_OK;
+}
+
+int32_t occrik_last_error_k(const occrik_plan* P) { return P ? P->last_err_k : -1; }
+
+occrik_status occrik_build(occrik_plan* P, const double* C, double* K, double* Kmi, double* Ex) {
+    if (!P || !C) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C");
+    DeviceGuard guard(P->device);
+    const size_t nC = (size_t)P->nk * P->nao * P->nocc * 2;
+    for (size_t i = 0; i < nC; ++i)
+        if (!std::isfinite(C[i])) return fail(OCCRIK_ERR_NONFINITE, "non-finite entries in C");
+    const size_t bC = nC * sizeof(double);
+    const size_t bK = (size_t)P->nk * P->nao * P->nao * 2 * sizeof(double);
+    void *dC = nullptr, *dK = nullptr, *dKmi = nullptr, *dEx = nullptr;
+    occrik_status st = OCCRIK_OK;
+    hipError_t e = hipMalloc(&dC, bC);
+    if (e == hipSuccess && K) e = hipMalloc(&dK, bK);
+    if (e == hipSuccess && Kmi) e = hipMalloc(&dKmi, bC);
+    if (e == hipSuccess && Ex) e = hipMalloc(&dEx, sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(dC, C, bC, hipMemcpyHostToDevice, P->stream);
+    if (e != hipSuccess) st = hip_fail(e, "occrik_build staging");
+    if (st == OCCRIK_OK) st = occrik_build_device(P, dC, dK, dKmi, (double*)dEx);
+    if (st == OCCRIK_OK) st = occrik_plan_status(P);
+    if (st == OCCRIK_OK) {
+        if (K) e = hipMemcpyAsync(K, dK, bK, hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess && Kmi) e = hipMemcpyAsync(Kmi, dKmi, bC, hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess && Ex) e = hipMemcpyAsync(Ex, dEx, sizeof(double), hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) st = hip_fail(e, "occrik_build readback");
+    }
+    (void)hipStreamSynchronize(P->stream);
+    if (dC) (void)hipFree(dC);
+    if (dK) (void)hipFree(dK);
+    if (dKmi) (void)hipFree(dKmi);
+    if (dEx) (void)hipFree(dEx);
+    return st;
+}
+
+occrik_status occrik_grad(occrik_plan* P, double gEx, void* dgradC, double* dgradOmega) {
+    if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    if (!P->built) return fail(OCCRIK_ERR_STATE, "occrik_grad needs a build on this plan first");
+    if (!std::isfinite(gEx)) return fail(OCCRIK_ERR_INVALID_ARG, "non-finite gEx");
+    DeviceGuard guard(P->device);
+    if (dgradC)
+        OCCRIK_HIP(launch_scale_copy(P->Kmi, (double2*)dgradC, (size_t)P->nk * P->nao * P->nocc, gEx * 2.0 / P->nk,
+                                     P->stream));
+    if (dgradOmega) {
+        double d = 0.0;
+        if (P->params.kernel != OCCRIK_KERNEL_COULOMB) {
+            occrik_status st = P->fp64 ? domega_impl<double>(P, &d) : domega_impl<float>(P, &d);
+            if (st != OCCRIK_OK) return st;
+        }
+        *dgradOmega = gEx * d;
+    }
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_build_batch(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                                 void* const* dKmi, double* const* dEx) {
+    if (n < 0 || (n > 0 && (!plans || !dC))) return fail(OCCRIK_ERR_INVALID_ARG, "bad batch arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !dC[i]) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C in batch");
+        if (plans[i]->device != plans[0]->device || plans[i]->stream != plans[0]->stream)
+            return fail(OCCRIK_ERR_INVALID_ARG, "batch plans must share device and stream");
+    }
+    for (int i = 0; i < n; ++i) {
+        occrik_status st = occrik_build_device(plans[i], dC[i], dK ? dK[i] : nullptr, dKmi ? dKmi[i] : nullptr,
+                                               dEx ? dEx[i] : nullptr);
+        if (st != OCCRIK_OK) return st;
+    }
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_set_profiling(occrik_plan* P, int32_t on) {
+    if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    P->profiling = on != 0;
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_get_profile(occrik_plan* P, occrik_profile* out, int32_t reset) {
+    if (!P || !out) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or out");
+    DeviceGuard guard(P->device);
+    for (auto& pe : P->prof) {
+        OCCRIK_HIP(hipEventSynchronize(pe.e[4]));
+        float t[4];
+        for (int i = 0; i < 4; ++i) OCCRIK_HIP(hipEventElapsedTime(&t[i], pe.e[i], pe.e[i + 1]));
+        P->prof_acc.ms_orbitals += t[0];
+        P->prof_acc.ms_pairs += t[1];
+        P->prof_acc.ms_contract += t[2];
+        P->prof_acc.ms_assemble += t[3];
+        P->prof_acc.launches_pairs += pe.pair_launches;
+        P->prof_acc.builds += 1;
+        for (auto& e : pe.e) (void)hipEventDestroy(e);
+    }
+    P->prof.clear();
+    *out = P->prof_acc;
+    if (reset) P->prof_acc = occrik_profile{};
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_copy_intermediate(occrik_plan* P, int32_t which, void* dst, size_t bytes) {
+    if (!P || !dst) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or dst");
+    DeviceGuard guard(P->device);
+    const void* src = nullptr;
+    size_t n = 0;
+    if (which == 0) {
+        src = P->chi;
+        n = (size_t)P->nk * P->nao * P->ng;
+    } else if (which == 1 || which == 2) {
+        if (!P->built) return fail(OCCRIK_ERR_STATE, "no build yet");
+        src = which == 1 ? P->psi : P->W;
+        n = (size_t)P->nk * P->nocc * P->ng;
+    } else {
+        return fail(OCCRIK_ERR_INVALID_ARG, "which must be 0, 1 or 2");
+    }
+    if (bytes != n * sizeof(double2)) return fail(OCCRIK_ERR_INVALID_ARG, "bytes does not match the array size");
+    if (P->fp64) OCCRIK_HIP(launch_convert_to_c128<double>((const cplx<double>*)src, (double2*)dst, n, P->stream));
+    else OCCRIK_HIP(launch_convert_to_c128<float>((const cplx<float>*)src, (double2*)dst, n, P->stream));
+    OCCRIK_HIP(hipStreamSynchronize(P->stream));
+    return OCCRIK_OK;
+}
+
+}  // extern "C"

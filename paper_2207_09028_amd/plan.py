@@ -1,0 +1,209 @@
+"""Python face of the occ-RI-K library: the same entry points as ``include/occrik.h``.
+
+PyTorch supplies device memory and the current HIP stream; every step of a
+build runs in the library's HIP kernels.  Arrays follow the C layouts:
+
+    C    [N_k, N_ao, nocc]  complex128  occupied coefficients
+    K    [N_k, N_ao, N_ao]  complex128  assembled exchange matrix K~
+    Kmi  [N_k, N_ao, nocc]  complex128  K_{mu j}
+    Ex   scalar float64                  exchange energy per cell and spin
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class PlanSpec:
+    lattice: np.ndarray            # (3, 3) bohr, rows a_1..a_3
+    atoms_frac: np.ndarray         # (natm, 3)
+    shell_atom: np.ndarray         # (nshell,)
+    shell_l: np.ndarray            # (nshell,)
+    shell_exp: np.ndarray          # (nshell,)
+    kmesh: tuple
+    grid: tuple
+    nocc: int
+    kernel: int = _lib.KERNEL_COULOMB
+    omega: float = 0.0
+    nyquist: int = _lib.NYQUIST_SYMMETRIC
+    precision: int = _lib.PREC_FP64
+    lattice_tol: float = 1e-12
+    kbatch: int = 0
+    mem_budget: int = 0
+
+    @classmethod
+    def from_problem(cls, prob, **overrides):
+        """From any object with cell/basis/kmesh/grid/nocc/kernel/omega/lattice_tol attributes."""
+        kw = dict(lattice=np.asarray(prob.cell.lattice, dtype=np.float64),
+                  atoms_frac=np.asarray(prob.cell.atoms_frac, dtype=np.float64),
+                  shell_atom=np.asarray(prob.basis.shell_atom, dtype=np.int32),
+                  shell_l=np.asarray(prob.basis.shell_l, dtype=np.int32),
+                  shell_exp=np.asarray(prob.basis.shell_exp, dtype=np.float64),
+                  kmesh=tuple(prob.kmesh), grid=tuple(prob.grid), nocc=int(prob.nocc),
+                  kernel=int(prob.kernel), omega=float(prob.omega), lattice_tol=float(prob.lattice_tol))
+        kw.update(overrides)
+        return cls(**kw)
+
+
+class Plan:
+    """An occ-RI-K plan on one GPU (wraps occrik_plan_create / occrik_plan_destroy)."""
+
+    def __init__(self, spec: PlanSpec, device=None):
+        lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the occ-RI-K library needs a HIP device")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.spec = spec
+        lat = np.ascontiguousarray(spec.lattice, dtype=np.float64).reshape(9)
+        self._atoms = np.ascontiguousarray(spec.atoms_frac, dtype=np.float64).reshape(-1)
+        self._sa = np.ascontiguousarray(spec.shell_atom, dtype=np.int32)
+        self._sl = np.ascontiguousarray(spec.shell_l, dtype=np.int32)
+        self._se = np.ascontiguousarray(spec.shell_exp, dtype=np.float64)
+        cell = _lib.Cell((ctypes.c_double * 9)(*lat), len(self._atoms) // 3,
+                         self._atoms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        basis = _lib.Basis(len(self._sl), self._sa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           self._sl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           self._se.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        params = _lib.Params((ctypes.c_int32 * 3)(*spec.kmesh), (ctypes.c_int32 * 3)(*spec.grid), int(spec.nocc),
+                             int(spec.kernel), float(spec.omega), int(spec.nyquist), int(spec.precision),
+                             float(spec.lattice_tol), int(spec.kbatch), 0, int(spec.mem_budget))
+        handle = _lib.PlanP()
+        with torch.cuda.device(self.device):
+            st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params),
+                                        self.device.index, _stream_handle(self.device), ctypes.byref(handle))
+        check(st)
+        self._h = handle
+        self._lib = lib
+        self.info = self.query()
+        self.nk, self.nao, self.nocc, self.ng = self.info.nk, self.info.nao, self.info.nocc, self.info.ng
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.occrik_plan_destroy(self._h)
+            self._h = _lib.PlanP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries --------------------------------------------------------------
+    def query(self):
+        info = _lib.PlanInfo()
+        check(self._lib.occrik_plan_query(self._h, ctypes.byref(info)))
+        return info
+
+    def _sync_stream(self):
+        check(self._lib.occrik_set_stream(self._h, _stream_handle(self.device)))
+
+    def set_omega(self, omega: float):
+        check(self._lib.occrik_set_omega(self._h, float(omega)))
+
+    # -- builds ---------------------------------------------------------------
+    def _check_C(self, C):
+        if not isinstance(C, torch.Tensor) or C.dtype != torch.complex128 or C.device != self.device:
+            raise TypeError("C must be a complex128 tensor on the plan's device")
+        if tuple(C.shape) != (self.nk, self.nao, self.nocc) or not C.is_contiguous():
+            raise ValueError(f"C must be contiguous with shape {(self.nk, self.nao, self.nocc)}")
+
+    def build_device(self, C, K=None, Kmi=None, Ex=None):
+        """occrik_build_device on caller tensors (asynchronous on the current stream)."""
+        self._check_C(C)
+        for t, shape in ((K, (self.nk, self.nao, self.nao)), (Kmi, (self.nk, self.nao, self.nocc))):
+            if t is not None and (t.dtype != torch.complex128 or tuple(t.shape) != shape or not t.is_contiguous()
+                                  or t.device != self.device):
+                raise ValueError(f"output must be contiguous complex128 {shape} on the plan's device")
+        if Ex is not None and (Ex.dtype != torch.float64 or Ex.numel() != 1 or Ex.device != self.device):
+            raise ValueError("Ex must be one float64 on the plan's device")
+        self._sync_stream()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        check(self._lib.occrik_build_device(self._h, ptr(C), ptr(K), ptr(Kmi), ptr(Ex)), self._h)
+
+    def status(self):
+        check(self._lib.occrik_plan_status(self._h), self._h)
+
+    def build(self, C, want_K=True, want_Kmi=True):
+        """Build and return dict(K, Kmi, Ex) as device tensors; raises on a deferred device error."""
+        dev = self.device
+        K = torch.empty((self.nk, self.nao, self.nao), dtype=torch.complex128, device=dev) if want_K else None
+        Kmi = torch.empty((self.nk, self.nao, self.nocc), dtype=torch.complex128, device=dev) if want_Kmi else None
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        self.build_device(C, K, Kmi, Ex)
+        self.status()
+        return dict(K=K, Kmi=Kmi, Ex=Ex)
+
+    def build_host(self, C: np.ndarray, want_K=True, want_Kmi=True):
+        """occrik_build: synchronous, host arrays in and out."""
+        C = np.ascontiguousarray(C, dtype=np.complex128)
+        if C.shape != (self.nk, self.nao, self.nocc):
+            raise ValueError("bad C shape")
+        K = np.empty((self.nk, self.nao, self.nao), np.complex128) if want_K else None
+        Kmi = np.empty((self.nk, self.nao, self.nocc), np.complex128) if want_Kmi else None
+        Ex = ctypes.c_double(0.0)
+        p = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
+        self._sync_stream()
+        check(self._lib.occrik_build(self._h, p(C), p(K), p(Kmi), ctypes.byref(Ex)), self._h)
+        return dict(K=K, Kmi=Kmi, Ex=Ex.value)
+
+    def grad(self, gEx=1.0, want_C=True, want_omega=False):
+        """occrik_grad after a build: dL/dC (device tensor) and dL/domega (float)."""
+        g = torch.empty((self.nk, self.nao, self.nocc), dtype=torch.complex128, device=self.device) if want_C else None
+        dw = ctypes.c_double(0.0)
+        self._sync_stream()
+        check(self._lib.occrik_grad(self._h, float(gEx), ctypes.c_void_p(g.data_ptr()) if g is not None else None,
+                                    ctypes.byref(dw) if want_omega else None))
+        return g, (dw.value if want_omega else None)
+
+    # -- diagnostics and profiling -----------------------------------------------
+    def intermediate(self, which: str):
+        idx = {"chi": 0, "psi": 1, "W": 2}[which]
+        rows = self.nao if idx == 0 else self.nocc
+        out = torch.empty((self.nk, rows, self.ng), dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        check(self._lib.occrik_copy_intermediate(self._h, idx, ctypes.c_void_p(out.data_ptr()),
+                                                 out.numel() * 16))
+        return out
+
+    def set_profiling(self, on: bool):
+        check(self._lib.occrik_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self, reset=True):
+        p = _lib.Profile()
+        check(self._lib.occrik_get_profile(self._h, ctypes.byref(p), 1 if reset else 0))
+        return {f: getattr(p, f) for f, _ in _lib.Profile._fields_}
+
+
+def build_batch(plans, Cs, Ks=None, Kmis=None, Exs=None):
+    """occrik_build_batch over plans that share the current stream."""
+    lib = _lib.load()
+    n = len(plans)
+    for p in plans:
+        p._sync_stream()
+    arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x.data_ptr()) if x is not None else None for x in xs])
+    hp = (_lib.PlanP * n)(*[p._h for p in plans])
+    none = [None] * n
+    st = lib.occrik_build_batch(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none))
+    check(st)
+
+
+def grid_size_supported(n: int) -> bool:
+    return bool(_lib.load().occrik_grid_size_supported(int(n)))
