@@ -147,6 +147,10 @@ typedef struct {
     double ms_assemble;           /* K_ij, Cholesky, K~, E_x */
     int64_t launches_pairs;       /* kernel launches inside ms_pairs */
     int64_t builds;               /* builds accumulated since the last reset */
+    /* per-kernel sums over every launch of the pair passes (profiling level 2) */
+    double ms_pass[3];            /* pass 1, pass 2, pass 3 (+ its W reduction) */
+    int64_t launches_pass[3];     /* launches of each pass */
+    double bytes_pass[3];         /* algorithmic HBM bytes moved by those launches */
 } occrik_profile;
 
 /* Create a plan: validates the inputs, derives the reciprocal lattice and the
@@ -212,9 +216,13 @@ occrik_status occrik_grad(occrik_plan *plan, double gEx, void *dgradC, double *d
 occrik_status occrik_build_batch(int32_t n, occrik_plan *const *plans, const void *const *dC,
                                  void *const *dK, void *const *dKmi, double *const *dEx);
 
-/* Profiling: when on, every build records HIP events around its phases on the
- * plan's stream; occrik_get_profile synchronises and returns the accumulated
- * milliseconds since the last reset (reset = 1 clears them afterwards). */
+/* Profiling: level 1 records HIP events around the phases of every build on
+ * the plan's stream; level 2 also brackets every pair-pass launch.
+ * occrik_get_profile synchronises and returns the accumulated milliseconds
+ * since the last reset (reset = 1 clears them afterwards).  Algorithmic bytes
+ * per launch: pass 1 writes P N_g s, pass 2 reads and writes P N_g s, pass 3
+ * reads P N_g s, for P = pairs in the launch and s = bytes per complex value
+ * (orbital-plane reads are not counted: they are shared by many pairs). */
 occrik_status occrik_set_profiling(occrik_plan *plan, int32_t on);
 occrik_status occrik_get_profile(occrik_plan *plan, occrik_profile *out, int32_t reset);
 

@@ -96,19 +96,21 @@ def pair_potentials(geo, rho, k2, k1, kind, omega, nyquist="fftfreq", want_parse
     return V, np.sum(v * np.abs(uhat) ** 2, axis=(-3, -2, -1))
 
 
-def exchange_w(geo, psi, out_k, kind, omega, nyquist="fftfreq", parseval=False, domega=False):
+def exchange_w(geo, psi, out_k, kind, omega, nyquist="fftfreq", parseval=False, domega=False, k1_subset=None):
     """Alg. 3 loops: W[k2][j] = sum_{k1, i} psi_{i k1} V_{i k1, j k2} for k2 in out_k.
 
     Also returns the Parseval partial sums sum f |u^|^2 (and sum df/dw |u^|^2) over
-    the same pairs, when requested.
+    the same pairs, when requested.  ``k1_subset`` restricts the summed k-points
+    (a partial sum, used only to time a bounded sample of the loops).
     """
     nocc = psi.shape[1]
     W = np.zeros((len(out_k), nocc, geo.ng), dtype=np.complex128)
     ps = 0.0
     pd = 0.0
+    k1_list = range(geo.nk) if k1_subset is None else list(k1_subset)
     for a, k2 in enumerate(out_k):
         for j in range(nocc):
-            for k1 in range(geo.nk):
+            for k1 in k1_list:
                 rho = np.conj(psi[k1]) * psi[k2, j][None, :]          # all i at once
                 V, s = pair_potentials(geo, rho, k2, k1, kind, omega, nyquist, want_parseval=parseval or domega)
                 W[a, j] += np.sum(psi[k1] * V, axis=0)

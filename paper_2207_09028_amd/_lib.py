@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms_orbitals", c_double), ("ms_pairs", c_double), ("ms_contract", c_double),
-                ("ms_assemble", c_double), ("launches_pairs", ctypes.c_int64), ("builds", ctypes.c_int64)]
+                ("ms_assemble", c_double), ("launches_pairs", ctypes.c_int64), ("builds", ctypes.c_int64),
+                ("ms_pass", c_double * 3), ("launches_pass", ctypes.c_int64 * 3), ("bytes_pass", c_double * 3)]
 
 
 PlanP = c_void_p

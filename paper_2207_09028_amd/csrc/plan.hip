@@ -58,6 +58,8 @@ struct DeviceGuard {
 struct ProfileEvents {
     hipEvent_t e[5];
     int64_t pair_launches;
+    std::vector<hipEvent_t> pe;    // level 2: 4 events per batch (before pass 1, after 1, 2, 3)
+    std::vector<double> pbytes;    // algorithmic bytes of each batch's passes (3 per batch)
 };
 
 }  // namespace
@@ -100,13 +102,15 @@ struct occrik_plan {
     int last_err_k = -1;
     double plan_seconds = 0.0;
 
-    bool profiling = false;
+    int profiling = 0;
     std::vector<ProfileEvents> prof;
     occrik_profile prof_acc{};
 
     ~occrik_plan() {
-        for (auto& p : prof)
+        for (auto& p : prof) {
             for (auto& e : p.e) (void)hipEventDestroy(e);
+            for (auto& e : p.pe) (void)hipEventDestroy(e);
+        }
         for (void* p : allocations) (void)hipFree(p);
     }
 
@@ -374,10 +378,25 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
         for (int b0 = 0; b0 < nk; b0 += P->kbatch) {
             const int nb = std::min(P->kbatch, nk - b0);
             PairBatch B = make_batch(P, a, b0, nb);
+            hipEvent_t ev[4] = {};
+            if (P->profiling >= 2) {
+                for (auto& e : ev) {
+                    OCCRIK_HIP(hipEventCreate(&e));
+                    pe.pe.push_back(e);
+                }
+                const double pb = double(nb) * nocc * nocc * ng * sizeof(cplx<T>);
+                pe.pbytes.push_back(pb);
+                pe.pbytes.push_back(2.0 * pb);
+                pe.pbytes.push_back(pb);
+                OCCRIK_HIP(hipEventRecord(ev[0], s));
+            }
             OCCRIK_HIP(launch_pass1<T>(B, psi, X, tw, s));
+            if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[1], s));
             OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 0, s));
+            if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[2], s));
             OCCRIK_HIP(launch_pass3<T>(B, X, psi, Wp, tw, s));
             OCCRIK_HIP(launch_wreduce<T>(B, Wp, W, s));
+            if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[3], s));
             launches += 4;
         }
     }
@@ -394,7 +413,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     if (P->profiling) {
         OCCRIK_HIP(hipEventRecord(pe.e[4], s));
         pe.pair_launches = launches;
-        P->prof.push_back(pe);
+        P->prof.push_back(std::move(pe));
     }
     P->built = true;
     return OCCRIK_OK;
@@ -722,7 +741,8 @@ occrik_status occrik_build_batch(int32_t n, occrik_plan* const* plans, const voi
 
 occrik_status occrik_set_profiling(occrik_plan* P, int32_t on) {
     if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
-    P->profiling = on != 0;
+    if (on < 0 || on > 2) return fail(OCCRIK_ERR_INVALID_ARG, "profiling level must be 0, 1 or 2");
+    P->profiling = on;
     return OCCRIK_OK;
 }
 
@@ -739,7 +759,17 @@ occrik_status occrik_get_profile(occrik_plan* P, occrik_profile* out, int32_t re
         P->prof_acc.ms_assemble += t[3];
         P->prof_acc.launches_pairs += pe.pair_launches;
         P->prof_acc.builds += 1;
+        for (size_t b = 0; b + 3 < pe.pe.size(); b += 4) {
+            for (int q = 0; q < 3; ++q) {
+                float ms = 0.f;
+                OCCRIK_HIP(hipEventElapsedTime(&ms, pe.pe[b + q], pe.pe[b + q + 1]));
+                P->prof_acc.ms_pass[q] += ms;
+                P->prof_acc.launches_pass[q] += 1;
+                P->prof_acc.bytes_pass[q] += pe.pbytes[3 * (b / 4) + q];
+            }
+        }
         for (auto& e : pe.e) (void)hipEventDestroy(e);
+        for (auto& e : pe.pe) (void)hipEventDestroy(e);
     }
     P->prof.clear();
     *out = P->prof_acc;

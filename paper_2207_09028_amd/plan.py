@@ -183,13 +183,17 @@ class Plan:
                                                  out.numel() * 16))
         return out
 
-    def set_profiling(self, on: bool):
-        check(self._lib.occrik_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, level: int):
+        check(self._lib.occrik_set_profiling(self._h, int(level)))
 
     def profile(self, reset=True):
         p = _lib.Profile()
         check(self._lib.occrik_get_profile(self._h, ctypes.byref(p), 1 if reset else 0))
-        return {f: getattr(p, f) for f, _ in _lib.Profile._fields_}
+        out = {}
+        for f, _ in _lib.Profile._fields_:
+            v = getattr(p, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 def build_batch(plans, Cs, Ks=None, Kmis=None, Exs=None):

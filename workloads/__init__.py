@@ -315,37 +315,50 @@ def overlap_k(prob: Problem) -> np.ndarray:
     rmax = np.sqrt(50.0 / pmin) + np.max(np.linalg.norm(lat, axis=1)) * 2
     inv = np.linalg.inv(lat)
     nmax = [int(np.ceil(rmax * np.linalg.norm(inv[:, d]))) + 1 for d in range(3)]
-    tr = np.stack(np.meshgrid(*[np.arange(-n, n + 1) for n in nmax], indexing="ij"), -1).reshape(-1, 3)
-    T_all = tr @ lat
+    tr_all = np.stack(np.meshgrid(*[np.arange(-n, n + 1) for n in nmax], indexing="ij"), -1).reshape(-1, 3)
+    # per atom pair: images sorted by distance, so every shell pair keeps a prefix
+    pair_cache = {}
+    for ia in range(cell.natm):
+        for ib in range(cell.natm):
+            d = centers[ia][None, :] - (centers[ib][None, :] + tr_all @ lat)
+            d2 = np.sum(d * d, axis=1)
+            order = np.argsort(d2, kind="stable")
+            tri = tr_all[order]
+            arg = 2.0 * np.pi * (kf @ tri.T)
+            pair_cache[(ia, ib)] = (tri @ lat, d2[order], np.cos(arg), np.sin(arg))
     for si in range(basis.nshell):
         la, a = int(basis.shell_l[si]), float(basis.shell_exp[si])
-        A = centers[basis.shell_atom[si]]
+        ia = int(basis.shell_atom[si])
+        A = centers[ia]
         ca = cart_components(la)
+        na_ = [cart_norm(a, *c) for c in ca]
         for sj in range(basis.nshell):
             lb, b = int(basis.shell_l[sj]), float(basis.shell_exp[sj])
-            B0 = centers[basis.shell_atom[sj]]
+            ib = int(basis.shell_atom[sj])
+            B0 = centers[ib]
             cb = cart_components(lb)
             p = a + b
             mu = a * b / p
-            d = A[None, :] - (B0[None, :] + T_all)
-            d2 = np.sum(d * d, axis=1)
-            keep = mu * d2 < 45.0 + 2.0 * (la + lb)
-            T = T_all[keep]
-            tri = tr[keep]
+            T_s, d2_s, cos_s, sin_s = pair_cache[(ia, ib)]
+            n = int(np.searchsorted(d2_s, (45.0 + 2.0 * (la + lb)) / mu, side="left"))
+            if n == 0:
+                continue
+            T = T_s[:n]
             Bs = B0[None, :] + T
             P = (a * A[None, :] + b * Bs) / p
             PA = P - A[None, :]
             PB = P - Bs
-            pref = (np.pi / p) ** 1.5 * np.exp(-mu * d2[keep])
+            pref = (np.pi / p) ** 1.5 * np.exp(-mu * d2_s[:n])
             tabs = [_os_1d(la, lb, PA[:, x], PB[:, x], p) for x in range(3)]
-            phase = np.exp(2j * np.pi * (kf @ tri.T))               # (nk, nT)
-            blk = np.zeros((len(ca), len(cb), T.shape[0]))
-            for ia, (ax, ay, az) in enumerate(ca):
-                na = cart_norm(a, ax, ay, az)
-                for ib, (bx, by, bz) in enumerate(cb):
+            blk = np.empty((len(ca) * len(cb), n))
+            for iaa, (ax, ay, az) in enumerate(ca):
+                for ibb, (bx, by, bz) in enumerate(cb):
                     nb = cart_norm(b, bx, by, bz)
-                    blk[ia, ib] = na * nb * pref * tabs[0][ax, bx] * tabs[1][ay, by] * tabs[2][az, bz]
-            S[:, offs[si]:offs[si] + len(ca), offs[sj]:offs[sj] + len(cb)] = np.einsum("kt,abt->kab", phase, blk)
+                    blk[iaa * len(cb) + ibb] = (na_[iaa] * nb) * pref * tabs[0][ax, bx] * tabs[1][ay, by] * tabs[2][az, bz]
+            re = cos_s[:, :n] @ blk.T
+            im = sin_s[:, :n] @ blk.T
+            S[:, offs[si]:offs[si] + len(ca), offs[sj]:offs[sj] + len(cb)] = (re + 1j * im).reshape(
+                prob.nk, len(ca), len(cb))
     return S
 
 
