@@ -21,7 +21,7 @@ namespace occrik {
 template <typename T, int R, int DIR> struct Dft;
 
 template <typename T, int DIR> struct Dft<T, 2, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         cplx<T> a = v[0], b = v[1];
         v[0] = cadd<T>(a, b);
         v[1] = csub<T>(a, b);
@@ -29,7 +29,7 @@ template <typename T, int DIR> struct Dft<T, 2, DIR> {
 };
 
 template <typename T, int DIR> struct Dft<T, 3, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         const T c = T(-0.5);
         const T s = T(0.86602540378443864676372317075294);
         cplx<T> t = cadd<T>(v[1], v[2]);
@@ -44,7 +44,7 @@ template <typename T, int DIR> struct Dft<T, 3, DIR> {
 };
 
 template <typename T, int DIR> struct Dft<T, 4, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         cplx<T> a = cadd<T>(v[0], v[2]);
         cplx<T> b = csub<T>(v[0], v[2]);
         cplx<T> c = cadd<T>(v[1], v[3]);
@@ -57,7 +57,7 @@ template <typename T, int DIR> struct Dft<T, 4, DIR> {
 };
 
 template <typename T, int DIR> struct Dft<T, 5, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         const T c1 = T(0.30901699437494742410229341718282);    // cos(2 pi / 5)
         const T c2 = T(-0.80901699437494742410229341718282);   // cos(4 pi / 5)
         const T s1 = T(0.95105651629515357211643933337938);    // sin(2 pi / 5)
@@ -79,7 +79,7 @@ template <typename T, int DIR> struct Dft<T, 5, DIR> {
 
 // 6 = 3 x 2: inner 3-point DFTs over x[2 n1 + n2], twiddle w6^{n2 k1}, outer 2-point.
 template <typename T, int DIR> struct Dft<T, 6, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         cplx<T> e[3] = {v[0], v[2], v[4]};
         cplx<T> o[3] = {v[1], v[3], v[5]};
         Dft<T, 3, DIR>::run(e);
@@ -99,7 +99,7 @@ template <typename T, int DIR> struct Dft<T, 6, DIR> {
 
 // 8 = 2 x 4: inner 2-point DFTs over (x[n2], x[n2 + 4]), twiddle w8^{n2 k1}, outer 4-point.
 template <typename T, int DIR> struct Dft<T, 8, DIR> {
-    static __device__ inline void run(cplx<T>* v) {
+    static __device__ __forceinline__ void run(cplx<T>* v) {
         cplx<T> y0[4], y1[4];
 #pragma unroll
         for (int n2 = 0; n2 < 4; ++n2) {
@@ -169,20 +169,37 @@ inline bool grid_size_supported(int n) {
     }
 }
 
-// One Stockham stage of radix R after sub-transforms of length NS.
-template <typename T, int N, int R, int NS, int DIR>
-__device__ inline void stockham_stage(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+// One Stockham stage of radix R after sub-transforms of length NS, run by NT
+// threads.  With the line count fixed at compile time (LINES > 0) work items
+// are numbered line-fastest, so the lanes of a wave touch consecutive lines:
+// consecutive LDS addresses when lines are adjacent (ls = 1) and a fixed
+// odd-padded stride when elements are adjacent (es = 1), both free of bank
+// conflicts.  With a run-time line count (LINES = 0, at most kMaxN lines) they
+// are numbered element-fastest, which needs no run-time division.
+template <typename T, int N, int R, int NS, int DIR, int LINES, int NT>
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
     constexpr int NB = N / R;                                   // butterflies per line
-    constexpr int ITEMS = (kMaxN * NB + kFftThreads - 1) / kFftThreads;
+    constexpr int MAXL = LINES > 0 ? LINES : kMaxN;
+    constexpr int ITEMS = (MAXL * NB + NT - 1) / NT;
     constexpr int TWS = N / (NS * R);                           // twiddle index step
+    if constexpr (LINES > 0) lines = LINES;
     cplx<T> v[ITEMS][R];
     const int total = lines * NB;
+    auto split = [&](int it, int& line, int& j) {
+        if constexpr (LINES > 0) {
+            j = it / LINES;
+            line = it - j * LINES;
+        } else {
+            line = it / NB;
+            j = it - line * NB;
+        }
+    };
 #pragma unroll
     for (int t = 0; t < ITEMS; ++t) {
-        const int it = threadIdx.x + t * kFftThreads;
+        const int it = threadIdx.x + t * NT;
         if (it < total) {
-            const int line = it / NB;
-            const int j = it - line * NB;
+            int line, j;
+            split(it, line, j);
             const cplx<T>* p = buf + line * ls;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[t][r] = p[(j + r * NB) * es];
@@ -191,10 +208,10 @@ __device__ inline void stockham_stage(cplx<T>* buf, int lines, int es, int ls, c
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < ITEMS; ++t) {
-        const int it = threadIdx.x + t * kFftThreads;
+        const int it = threadIdx.x + t * NT;
         if (it < total) {
-            const int line = it / NB;
-            const int j = it - line * NB;
+            int line, j;
+            split(it, line, j);
             const int jm = j % NS;
             if (NS > 1) {
 #pragma unroll
@@ -216,45 +233,35 @@ __device__ inline void stockham_stage(cplx<T>* buf, int lines, int es, int ls, c
 
 // Full transform of length N along every line of the tile.  The caller must
 // have synchronised after writing the tile; the tile is ready on return.
-template <typename T, int N, int DIR>
-__device__ inline void fft_lines(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+template <typename T, int N, int DIR, int LINES = 0, int NT = kFftThreads>
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
     using S = Sched<N>;
-    stockham_stage<T, N, S::r0, 1, DIR>(buf, lines, es, ls, tw);
-    if constexpr (S::r1 != 0) stockham_stage<T, N, S::r1, S::r0, DIR>(buf, lines, es, ls, tw);
-    if constexpr (S::r2 != 0) stockham_stage<T, N, S::r2, S::r0 * S::r1, DIR>(buf, lines, es, ls, tw);
+    stockham_stage<T, N, S::r0, 1, DIR, LINES, NT>(buf, lines, es, ls, tw);
+    if constexpr (S::r1 != 0) stockham_stage<T, N, S::r1, S::r0, DIR, LINES, NT>(buf, lines, es, ls, tw);
+    if constexpr (S::r2 != 0) stockham_stage<T, N, S::r2, S::r0 * S::r1, DIR, LINES, NT>(buf, lines, es, ls, tw);
+}
+
+// Run-time length dispatch for grids without a compile-time specialisation.
+// Each length is a separate out-of-line function so that the caller does not
+// carry the register footprint of every length at once.
+template <typename T, int N, int DIR>
+__device__ __noinline__ void fft_lines_out_of_line(cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+    fft_lines<T, N, DIR>(buf, lines, es, ls, tw);
 }
 
 template <typename T, int DIR>
 __device__ inline void fft_lines_n(int n, cplx<T>* buf, int lines, int es, int ls, const cplx<T>* tw) {
+#define OCCRIK_CASE(N_) \
+    case N_: fft_lines_out_of_line<T, N_, DIR>(buf, lines, es, ls, tw); break;
     switch (n) {
-        case 2: fft_lines<T, 2, DIR>(buf, lines, es, ls, tw); break;
-        case 3: fft_lines<T, 3, DIR>(buf, lines, es, ls, tw); break;
-        case 4: fft_lines<T, 4, DIR>(buf, lines, es, ls, tw); break;
-        case 5: fft_lines<T, 5, DIR>(buf, lines, es, ls, tw); break;
-        case 6: fft_lines<T, 6, DIR>(buf, lines, es, ls, tw); break;
-        case 8: fft_lines<T, 8, DIR>(buf, lines, es, ls, tw); break;
-        case 9: fft_lines<T, 9, DIR>(buf, lines, es, ls, tw); break;
-        case 10: fft_lines<T, 10, DIR>(buf, lines, es, ls, tw); break;
-        case 12: fft_lines<T, 12, DIR>(buf, lines, es, ls, tw); break;
-        case 15: fft_lines<T, 15, DIR>(buf, lines, es, ls, tw); break;
-        case 16: fft_lines<T, 16, DIR>(buf, lines, es, ls, tw); break;
-        case 18: fft_lines<T, 18, DIR>(buf, lines, es, ls, tw); break;
-        case 20: fft_lines<T, 20, DIR>(buf, lines, es, ls, tw); break;
-        case 24: fft_lines<T, 24, DIR>(buf, lines, es, ls, tw); break;
-        case 25: fft_lines<T, 25, DIR>(buf, lines, es, ls, tw); break;
-        case 27: fft_lines<T, 27, DIR>(buf, lines, es, ls, tw); break;
-        case 30: fft_lines<T, 30, DIR>(buf, lines, es, ls, tw); break;
-        case 32: fft_lines<T, 32, DIR>(buf, lines, es, ls, tw); break;
-        case 36: fft_lines<T, 36, DIR>(buf, lines, es, ls, tw); break;
-        case 40: fft_lines<T, 40, DIR>(buf, lines, es, ls, tw); break;
-        case 45: fft_lines<T, 45, DIR>(buf, lines, es, ls, tw); break;
-        case 48: fft_lines<T, 48, DIR>(buf, lines, es, ls, tw); break;
-        case 50: fft_lines<T, 50, DIR>(buf, lines, es, ls, tw); break;
-        case 54: fft_lines<T, 54, DIR>(buf, lines, es, ls, tw); break;
-        case 60: fft_lines<T, 60, DIR>(buf, lines, es, ls, tw); break;
-        case 64: fft_lines<T, 64, DIR>(buf, lines, es, ls, tw); break;
+        OCCRIK_CASE(2) OCCRIK_CASE(3) OCCRIK_CASE(4) OCCRIK_CASE(5) OCCRIK_CASE(6) OCCRIK_CASE(8)
+        OCCRIK_CASE(9) OCCRIK_CASE(10) OCCRIK_CASE(12) OCCRIK_CASE(15) OCCRIK_CASE(16) OCCRIK_CASE(18)
+        OCCRIK_CASE(20) OCCRIK_CASE(24) OCCRIK_CASE(25) OCCRIK_CASE(27) OCCRIK_CASE(30) OCCRIK_CASE(32)
+        OCCRIK_CASE(36) OCCRIK_CASE(40) OCCRIK_CASE(45) OCCRIK_CASE(48) OCCRIK_CASE(50) OCCRIK_CASE(54)
+        OCCRIK_CASE(60) OCCRIK_CASE(64)
         default: break;                                   // n == 1: identity
     }
+#undef OCCRIK_CASE
 }
 
 }  // namespace occrik

@@ -13,22 +13,34 @@
 
 namespace occrik {
 
-// Geometry of one batch of pair round trips: output k-point a, summed k-points
-// b in [b0, b0 + nb), all nocc x nocc orbital pairs.  Pair p of the batch is
-// ((b - b0) * nocc + i) * nocc + j: i the summed orbital at b, j the output
-// orbital at a.  Its density is conj(psi~_{i b}) psi~_{j a}, momentum q = k_a - k_b.
+// One batch of pair round trips: output k-point a, blocks (a, b) for b in
+// [b0, b0 + nb).  Stored pairs ("slots"): block b holds the nocc x nocc pairs
+// (i at b, j at a) at slot base + i * nocc + j; with conjugate-pair reuse the
+// batch starts at b0 >= a and, when b0 == a, the diagonal block comes first and
+// holds only the pairs i <= j (nocc (nocc + 1) / 2 slots, upper-triangle rows).
+// The density of a slot is conj(psi~_{i b}) psi~_{j a}, momentum q = k_a - k_b.
 struct PairBatch {
     int N1, N2, N3, ng;
     int M1, M2, M3;
     int nocc;
     int a, b0, nb;
+    int reuse;                // conjugate-pair reuse (symmetric Nyquist mode)
+    int diag;                 // the first block is the diagonal block (a, a)
+    int ntri;                 // nocc (nocc + 1) / 2
+    int nslots;               // stored pairs in the batch
+    int group;                // stored pairs per pass-2 workgroup
     int kernel, nyquist;
     double omega;
     double inv_ng;
     double recip[9];          // reciprocal vectors b_1, b_2, b_3 (rows)
-    int splits;               // pass-3 splits of the (b, i) sum
+    int splits;               // pass-3 splits of the (b, i) sum of the a-side
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
 };
+
+// pass-2 workgroups per m2-slab of a batch
+int pair_groups(const PairBatch& B);
+// pass-3 splits of the (b, i) sum for a batch (B.nb, B.nocc and the grid set), elem = bytes per complex
+int pass3_splits(const PairBatch& B, int elem);
 
 // Launchers (templated on the working real type: float or double).
 template <typename T>
@@ -37,8 +49,8 @@ template <typename T>
 hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
                         hipStream_t s);
 template <typename T>
-hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, const cplx<T>* tw,
-                        hipStream_t s);
+hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
+                        const cplx<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);
 

@@ -4,19 +4,27 @@
 // A 3D transform of N_1 x N_2 x N_3 points does not fit one CU's LDS, so each
 // forward + inverse round trip exchanges the data through device memory twice:
 //
-//   pass 1  (one x-plane n1 of one pair per workgroup)
+//   pass 1  (one x-plane n1 of one stored pair per workgroup)
 //           u = conj(psi~_{i b}) psi~_{j a} on the plane, FFT along n3 and n2,
-//           store X[p][n1][m2][m3]
-//   pass 2  (one m2-slab of one pair per workgroup, in place)
-//           FFT along n1, multiply by f(|G+q|)/N_g (computed on the fly, with
-//           the G+q=0 and Nyquist rules), inverse FFT along m1 and m3,
-//           store X[p][n1][m2][n3]
-//   pass 3  (one x-plane of one output orbital j, a slice of the (b, i) sum)
-//           inverse FFT along m2, multiply by psi~_{i b}, accumulate over the
-//           slice in registers: W~_j partial for this plane
+//           store X[slot][n1][m2][m3]
+//   pass 2  (one m2-slab of a group of stored pairs of one (a, b) block per
+//           workgroup, in place) the kernel f(|G+q|)/N_g is evaluated once per
+//           slab and reused for every pair of the group; FFT along n1, multiply,
+//           inverse FFT along m1 and m3, store X[slot][n1][m2][n3]
+//   pass 3  inverse FFT along m2 of each plane, multiply by the partner orbital
+//           and accumulate: W~_{j a} (a-side, split over the (b, i) sum, partial
+//           sums reduced in a fixed order) and, with conjugate-pair reuse,
+//           W~_{i b} += psi~_{j a} conj(Vt_ij) (b-side, one workgroup per plane)
 //
 // The potential Vt = IDFT(f DFT(u)) / N_g is the cell-periodic part of V;
 // psi~_{i b} Vt is the cell-periodic part of psi_{i b} V, so W~ = e^{-ik_a.r} W.
+//
+// Conjugate-pair reuse (symmetric Nyquist mode only, where it is exact): the
+// density of (k_b, k_a, j, i) is the conjugate of that of (k_a, k_b, i, j) and
+// its potential is the conjugate potential.  A batch then covers the blocks
+// (a, b) with b >= a; the diagonal block stores the pairs i <= j only.
+#include <algorithm>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -79,43 +87,88 @@ __device__ inline T momentum_sq(const Recip<T>& rc, double q0, double q1, double
     return gx * gx + gy * gy + gz * gz;
 }
 
+// Sizes: compile-time when NN > 0 (cubic NN^3 grid), else taken from the batch.
+template <int NN>
+struct Dims {
+    int n1, n2, n3;
+    __device__ explicit Dims(const PairBatch& B)
+        : n1(NN ? NN : B.N1), n2(NN ? NN : B.N2), n3(NN ? NN : B.N3) {}
+};
+
+template <typename T, int NN, int DIR>
+__device__ __forceinline__ void lines(int n, cplx<T>* buf, int count, int es, int ls, const cplx<T>* tw) {
+    if constexpr (NN > 0) fft_lines<T, NN, DIR, NN>(buf, count, es, ls, tw);
+    else fft_lines_n<T, DIR>(n, buf, count, es, ls, tw);
+}
+
+// index of the stored pair (i, j), i <= j, of a diagonal block: rows of the upper triangle
+__device__ inline int tri_index(int i, int j, int nocc) { return i * nocc - (i * (i - 1)) / 2 + (j - i); }
+
+// Stored pair slot -> (b, i, j).
+__device__ inline void decode_slot(const PairBatch& B, int slot, int& b, int& i, int& j) {
+    const int nn = B.nocc * B.nocc;
+    if (B.diag && slot < B.ntri) {
+        int r = 0;
+        while (r + 1 < B.nocc && tri_index(r + 1, r + 1, B.nocc) <= slot) ++r;
+        b = B.a;
+        i = r;
+        j = r + (slot - tri_index(r, r, B.nocc));
+        return;
+    }
+    const int s = slot - (B.diag ? B.ntri : 0);
+    const int blk = s / nn;
+    const int rem = s - blk * nn;
+    b = B.b0 + (B.diag ? 1 : 0) + blk;
+    i = rem / B.nocc;
+    j = rem - i * B.nocc;
+}
+
 // ---------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const cplx<T>* __restrict__ psi,
                                                             cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* plane = tw + 3 * kMaxN;
-    const int N2 = B.N2, N3 = B.N3, S = N3 + 1;
+    const Dims<NN> D(B);
+    const int N2 = D.n2, N3 = D.n3, S = N3 + 1;
     const int plane_sz = N2 * N3;
-    const int n1 = blockIdx.x % B.N1;
-    const int p = blockIdx.x / B.N1;
-    const int j = p % B.nocc;
-    const int i = (p / B.nocc) % B.nocc;
-    const int b = B.b0 + p / (B.nocc * B.nocc);
+    const int n1 = blockIdx.x % D.n1;
+    const int slot = blockIdx.x / D.n1;
+    int b, i, j;
+    decode_slot(B, slot, b, i, j);
     load_twiddles<T>(tw, twg);
     const cplx<T>* pj = psi + ((size_t)B.a * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
     const cplx<T>* pi = psi + ((size_t)b * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
-    for (int e = threadIdx.x; e < plane_sz; e += kFftThreads) {
-        const int n2 = e / N3, n3 = e - n2 * N3;
-        plane[n2 * S + n3] = cjmul<T>(pi[e], pj[e]);
+    constexpr int PTS = ((NN > 0 ? NN * NN : kMaxN * kMaxN) + kFftThreads - 1) / kFftThreads;
+#pragma unroll
+    for (int t = 0; t < PTS; ++t) {
+        const int e = threadIdx.x + t * kFftThreads;
+        if (e < plane_sz) {
+            const int n2 = e / N3, n3 = e - n2 * N3;
+            plane[n2 * S + n3] = cjmul<T>(pi[e], pj[e]);
+        }
     }
     __syncthreads();
-    fft_lines_n<T, -1>(N3, plane, N2, 1, S, tw + 2 * kMaxN);
-    fft_lines_n<T, -1>(N2, plane, N3, S, 1, tw + kMaxN);
-    cplx<T>* out = X + (size_t)p * B.ng + (size_t)n1 * plane_sz;
-    for (int e = threadIdx.x; e < plane_sz; e += kFftThreads) {
-        const int m2 = e / N3, m3 = e - m2 * N3;
-        out[e] = plane[m2 * S + m3];
+    lines<T, NN, -1>(N3, plane, N2, 1, S, tw + 2 * kMaxN);
+    lines<T, NN, -1>(N2, plane, N3, S, 1, tw + kMaxN);
+    cplx<T>* out = X + (size_t)slot * B.ng + (size_t)n1 * plane_sz;
+#pragma unroll
+    for (int t = 0; t < PTS; ++t) {
+        const int e = threadIdx.x + t * kFftThreads;
+        if (e < plane_sz) {
+            const int m2 = e / N3, m3 = e - m2 * N3;
+            out[e] = plane[m2 * S + m3];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>* __restrict__ X,
                                                             const cplx<T>* __restrict__ twg,
                                                             double* __restrict__ parts, int deriv_only) {
@@ -123,21 +176,33 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
     double* red = reinterpret_cast<double*>(tw + 3 * kMaxN);
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(red + kFftThreads);
-    const int N1 = B.N1, N2 = B.N2, N3 = B.N3, S = N3 + 1;
+    constexpr int ITEMS = (kMaxN * kMaxN + kFftThreads - 1) / kFftThreads;
+    constexpr int VI = NN > 0 ? (NN * NN + kFftThreads - 1) / kFftThreads : ITEMS;
+    const Dims<NN> D(B);
+    const int N1 = D.n1, N2 = D.n2, N3 = D.n3, S = N3 + 1;
     const int m2i = blockIdx.x % N2;
-    const int p = blockIdx.x / N2;
-    const int b = B.b0 + p / (B.nocc * B.nocc);
-    load_twiddles<T>(tw, twg);
-    cplx<T>* base = X + (size_t)p * B.ng + (size_t)m2i * N3;
-    const size_t rs = (size_t)N2 * N3;
-    const int tile_sz = N1 * N3;
-    for (int e = threadIdx.x; e < tile_sz; e += kFftThreads) {
-        const int n1 = e / N3, m3 = e - n1 * N3;
-        tile[n1 * S + m3] = base[n1 * rs + m3];
+    const int grp = blockIdx.x / N2;
+    // group -> (block, first slot, slot count); the diagonal block (if any) comes first
+    const int P = B.group;
+    const int nn = B.nocc * B.nocc;
+    const int gd = B.diag ? (B.ntri + P - 1) / P : 0;
+    const int go = (nn + P - 1) / P;
+    int s0, s1, b;
+    if (grp < gd) {
+        s0 = grp * P;
+        s1 = min(B.ntri, s0 + P);
+        b = B.a;
+    } else {
+        const int g = grp - gd;
+        const int blk = g / go;
+        const int base = (B.diag ? B.ntri : 0) + blk * nn;
+        s0 = base + (g - blk * go) * P;
+        s1 = min(base + nn, s0 + P);
+        b = B.b0 + (B.diag ? 1 : 0) + blk;
     }
-    __syncthreads();
-    fft_lines_n<T, -1>(N1, tile, N3, S, 1, tw);
+    load_twiddles<T>(tw, twg);
 
+    // kernel values of this slab, shared by every pair of the group
     double qa[3], qb[3];
     kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
     kfrac_of(b, B.M1, B.M2, B.M3, qb);
@@ -148,33 +213,82 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
     const int m2 = freq(m2i, N2);
     const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
+    const int tile_sz = N1 * N3;
+    T v[VI];
+#pragma unroll
+    for (int t = 0; t < VI; ++t) {
+        const int e = threadIdx.x + t * kFftThreads;
+        v[t] = T(0);
+        if (e < tile_sz) {
+            const int t1 = e / N3, t3 = e - t1 * N3;
+            const int m1 = freq(t1, N1), m3 = freq(t3, N3);
+            const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
+            const bool nyq = sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3));
+            T f = deriv_only ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
+            if (nyq) {
+                const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
+                const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
+                const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
+                const T x2m = momentum_sq<T>(rc, q0, q1, q2, mm1, mm2, mm3);
+                f = T(0.5) * (f + (deriv_only ? kernel_dfdw<T>(x2m, B.kernel, om) : kernel_f<T>(x2m, B.kernel, om)));
+            }
+            v[t] = f;
+        }
+    }
     const T scale = T(B.inv_ng);
+    const size_t rs = (size_t)N2 * N3;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < tile_sz; e += kFftThreads) {
-        const int t1 = e / N3, t3 = e - t1 * N3;
-        const int m1 = freq(t1, N1), m3 = freq(t3, N3);
-        const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
-        const bool nyq = sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3));
-        T x2m = x2;
-        if (nyq) {
-            const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
-            const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
-            const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
-            x2m = momentum_sq<T>(rc, q0, q1, q2, mm1, mm2, mm3);
+    for (int slot = s0; slot < s1; ++slot) {
+        // weight of this stored pair in the full (k, k', i, j) sum
+        double wgt = 1.0;
+        if (B.reuse) {
+            if (b != B.a) wgt = 2.0;
+            else {
+                int bb, ii, jj;
+                decode_slot(B, slot, bb, ii, jj);
+                wgt = ii == jj ? 1.0 : 2.0;
+            }
         }
-        cplx<T> u = tile[t1 * S + t3];
-        if (deriv_only) {
-            T d = kernel_dfdw<T>(x2, B.kernel, om);
-            if (nyq) d = T(0.5) * (d + kernel_dfdw<T>(x2m, B.kernel, om));
-            acc += double(d) * (double(u.x) * double(u.x) + double(u.y) * double(u.y));
-            continue;
+        cplx<T>* base = X + (size_t)slot * B.ng + (size_t)m2i * N3;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < VI; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            if (e < tile_sz) {
+                const int n1 = e / N3, m3 = e - n1 * N3;
+                tile[n1 * S + m3] = base[n1 * rs + m3];
+            }
         }
-        T f = kernel_f<T>(x2, B.kernel, om);
-        if (nyq) f = T(0.5) * (f + kernel_f<T>(x2m, B.kernel, om));
-        if (B.parseval) acc += double(f) * (double(u.x) * double(u.x) + double(u.y) * double(u.y));
-        tile[t1 * S + t3] = cscale<T>(u, f * scale);
+        __syncthreads();
+        lines<T, NN, -1>(N1, tile, N3, S, 1, tw);
+        double pacc = 0.0;
+#pragma unroll
+        for (int t = 0; t < VI; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            if (e < tile_sz) {
+                const int t1 = e / N3, t3 = e - t1 * N3;
+                const cplx<T> u = tile[t1 * S + t3];
+                if (deriv_only || B.parseval)
+                    pacc += double(v[t]) * (double(u.x) * double(u.x) + double(u.y) * double(u.y));
+                if (!deriv_only) tile[t1 * S + t3] = cscale<T>(u, v[t] * scale);
+            }
+        }
+        acc += wgt * pacc;
+        if (deriv_only) continue;
+        __syncthreads();
+        lines<T, NN, +1>(N1, tile, N3, S, 1, tw);
+        lines<T, NN, +1>(N3, tile, N1, 1, S, tw + 2 * kMaxN);
+#pragma unroll
+        for (int t = 0; t < VI; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            if (e < tile_sz) {
+                const int n1 = e / N3, n3 = e - n1 * N3;
+                base[n1 * rs + n3] = tile[n1 * S + n3];
+            }
+        }
     }
     if (B.parseval || deriv_only) {
+        __syncthreads();
         red[threadIdx.x] = acc;
         __syncthreads();
         for (int w = kFftThreads / 2; w > 0; w >>= 1) {
@@ -183,69 +297,238 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
         }
         if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
     }
-    if (deriv_only) return;
-    __syncthreads();
-    fft_lines_n<T, +1>(N1, tile, N3, S, 1, tw);
-    fft_lines_n<T, +1>(N3, tile, N1, 1, S, tw + 2 * kMaxN);
-    for (int e = threadIdx.x; e < tile_sz; e += kFftThreads) {
-        const int n1 = e / N3, n3 = e - n1 * N3;
-        base[n1 * rs + n3] = tile[n1 * S + n3];
-    }
 }
 
 // ---------------------------------------------------------------------------
 // pass 3
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const cplx<T>* __restrict__ X,
                                                             const cplx<T>* __restrict__ psi,
-                                                            cplx<T>* __restrict__ Wpart,
+                                                            cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
                                                             const cplx<T>* __restrict__ twg) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* plane = tw + 3 * kMaxN;
-    constexpr int ACC = (kMaxN * kMaxN + kFftThreads - 1) / kFftThreads;
-    const int N2 = B.N2, N3 = B.N3, S = N3 + 1;
+    constexpr int ACC0 = (kMaxN * kMaxN + kFftThreads - 1) / kFftThreads;
+    constexpr int ACC = NN > 0 ? (NN * NN + kFftThreads - 1) / kFftThreads : ACC0;
+    const Dims<NN> D(B);
+    const int N2 = D.n2, N3 = D.n3, S = N3 + 1;
     const int plane_sz = N2 * N3;
-    const int n1 = blockIdx.x % B.N1;
-    const int j = (blockIdx.x / B.N1) % B.nocc;
-    const int s = blockIdx.x / (B.N1 * B.nocc);
-    const int total = B.nb * B.nocc;
-    const int chunk = (total + B.splits - 1) / B.splits;
-    const int q0 = s * chunk;
-    const int q1 = min(total, q0 + chunk);
+    const int nA = D.n1 * B.nocc * B.splits;
+    const int nn = B.nocc * B.nocc;
+    const int first_full = B.b0 + (B.diag ? 1 : 0);
+    const int full_base = B.diag ? B.ntri : 0;
     load_twiddles<T>(tw, twg);
     cplx<T> acc[ACC];
 #pragma unroll
     for (int t = 0; t < ACC; ++t) acc[t] = mk<T>(T(0), T(0));
-    for (int q = q0; q < q1; ++q) {
-        const int bb = q / B.nocc, i = q - bb * B.nocc;
-        const int p = q * B.nocc + j;
-        const cplx<T>* src = X + (size_t)p * B.ng + (size_t)n1 * plane_sz;
-        for (int e = threadIdx.x; e < plane_sz; e += kFftThreads) {
+
+    // one term: acc += partner(plane) * (conj?)(IDFT_m2 X[slot] plane)
+    auto term = [&](int slot, bool conj_v, const cplx<T>* partner, int n1) {
+        const cplx<T>* src = X + (size_t)slot * B.ng + (size_t)n1 * plane_sz;
+    #pragma unroll
+    for (int e = threadIdx.x; e < plane_sz; e += kFftThreads) {
             const int m2 = e / N3, n3 = e - m2 * N3;
             plane[m2 * S + n3] = src[e];
         }
         __syncthreads();
-        fft_lines_n<T, +1>(N2, plane, N3, S, 1, tw + kMaxN);
-        const cplx<T>* pi = psi + ((size_t)(B.b0 + bb) * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+        lines<T, NN, +1>(N2, plane, N3, S, 1, tw + kMaxN);
 #pragma unroll
         for (int t = 0; t < ACC; ++t) {
             const int e = threadIdx.x + t * kFftThreads;
             if (e < plane_sz) {
                 const int n2 = e / N3, n3 = e - n2 * N3;
-                const cplx<T> v = plane[n2 * S + n3];
-                const cplx<T> w = pi[e];
+                cplx<T> v = plane[n2 * S + n3];
+                if (conj_v) v.y = -v.y;
+                const cplx<T> w = partner[e];
                 acc[t] = mk<T>(acc[t].x + w.x * v.x - w.y * v.y, acc[t].y + w.x * v.y + w.y * v.x);
             }
         }
         __syncthreads();
-    }
-    cplx<T>* out = Wpart + ((size_t)s * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
+    };
+
+    if ((int)blockIdx.x < nA) {
+        // a-side: W~_{j a}(plane n1) partial over a slice of the (b, i) sum
+        const int n1 = blockIdx.x % D.n1;
+        const int j = (blockIdx.x / D.n1) % B.nocc;
+        const int s = blockIdx.x / (D.n1 * B.nocc);
+        const int total = B.nb * B.nocc;
+        const int chunk = (total + B.splits - 1) / B.splits;
+        const int q0 = s * chunk;
+        const int q1 = min(total, q0 + chunk);
+        for (int q = q0; q < q1; ++q) {
+            const int bb = B.b0 + q / B.nocc, i = q % B.nocc;
+            int slot;
+            bool cj = false;
+            if (B.diag && bb == B.a) {
+                if (i <= j) slot = tri_index(i, j, B.nocc);
+                else {
+                    slot = tri_index(j, i, B.nocc);
+                    cj = true;
+                }
+            } else {
+                slot = full_base + (bb - first_full) * nn + i * B.nocc + j;
+            }
+            const cplx<T>* pi = psi + ((size_t)bb * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+            term(slot, cj, pi, n1);
+        }
+        cplx<T>* out = Wpart + ((size_t)s * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
 #pragma unroll
-    for (int t = 0; t < ACC; ++t) {
-        const int e = threadIdx.x + t * kFftThreads;
-        if (e < plane_sz) out[e] = acc[t];
+        for (int t = 0; t < ACC; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            if (e < plane_sz) out[e] = acc[t];
+        }
+    } else {
+        // b-side (reuse only): W~_{i b}(plane n1) += sum_j psi~_{j a} conj(Vt_ij)
+        const int g = blockIdx.x - nA;
+        const int n1 = g % D.n1;
+        const int i = (g / D.n1) % B.nocc;
+        const int blk = g / (D.n1 * B.nocc);
+        const int bb = first_full + blk;
+        for (int j = 0; j < B.nocc; ++j) {
+            const int slot = full_base + blk * nn + i * B.nocc + j;
+            const cplx<T>* pj = psi + ((size_t)B.a * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
+            term(slot, true, pj, n1);
+        }
+        cplx<T>* out = W + ((size_t)bb * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+#pragma unroll
+        for (int t = 0; t < ACC; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            if (e < plane_sz) out[e] = cadd<T>(out[e], acc[t]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 3, fused form for compile-time cubic grids
+// ---------------------------------------------------------------------------
+// One workgroup owns an x-plane n1, a block of WB adjacent n3 columns (WB
+// complex values = 128 bytes, one cache line per row) and a slice of the
+// (b, i) pairs of the batch.  For each (b, i) it loads the column block of the
+// potentials of all output orbitals j at once, runs one batched inverse FFT
+// along m2 over JC * WB lines, then
+//   a-side  acc_j += psi~_{i b} Vt_ij            (registers, all j of the slice)
+//   b-side  W~_{i b} += sum_j psi~_{j a} conj(Vt_ij)   (conjugate-pair reuse)
+// so every stored potential is read from device memory once and the partner
+// orbital psi~_{i b} once per (b, i) rather than once per j.
+constexpr int kPass3Threads = 1024;   // fused pass 3: 16 waves, a few rows per thread
+
+constexpr int colblock(int n, int elem) {
+    int w = 128 / elem;
+    while (w > 1 && n % w != 0) --w;
+    return w;
+}
+
+constexpr int pow2_at_least(int n) {
+    int p = 1;
+    while (p < n) p *= 2;
+    return p;
+}
+
+template <typename T, int NN, int JC>
+__global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, const cplx<T>* __restrict__ X,
+                                                             const cplx<T>* __restrict__ psi,
+                                                             cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
+                                                             const cplx<T>* __restrict__ twg) {
+    constexpr int WB = colblock(NN, (int)sizeof(cplx<T>));
+    constexpr int NCB = NN / WB;
+    constexpr int LN = JC * WB;                      // FFT lines of the tile: (j, column)
+    constexpr int LNP = pow2_at_least(LN);           // padded line count (divides the thread count)
+    static_assert(LNP <= kPass3Threads, "tile lines exceed the workgroup");
+    constexpr int RPI = kPass3Threads / LNP;           // rows per sweep of the workgroup
+    constexpr int PT = (NN + RPI - 1) / RPI;         // rows per thread
+    constexpr int PLANE = NN * NN;
+    constexpr int BP = NN * WB;                      // points of one column block
+    constexpr int BPT = (BP + kPass3Threads - 1) / kPass3Threads;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tile = tw + 3 * kMaxN;                  // tile[m2][LNP]
+    const int n1 = blockIdx.x % NN;
+    const int cb = (blockIdx.x / NN) % NCB;
+    const int s = blockIdx.x / (NN * NCB);
+    const int c0 = cb * WB;
+    const int nocc = B.nocc;
+    const int nn = nocc * nocc;
+    const int total = B.nb * nocc;
+    const int chunk = (total + B.splits - 1) / B.splits;
+    const int q0 = s * chunk;
+    const int q1 = min(total, q0 + chunk);
+    const int first_full = B.b0 + (B.diag ? 1 : 0);
+    const int full_base = B.diag ? B.ntri : 0;
+    // this thread's fixed (orbital, column) lane and first row
+    const int lane = threadIdx.x % LNP;
+    const int r0 = threadIdx.x / LNP;
+    const int jl = lane / WB;
+    const int w = lane - jl * WB;
+    const bool active = lane < LN && jl < nocc;
+    load_twiddles<T>(tw, twg);
+    const size_t plane_off = (size_t)n1 * PLANE + c0 + w;
+    cplx<T> acc[PT];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) acc[t] = mk<T>(T(0), T(0));
+
+    for (int q = q0; q < q1; ++q) {
+        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        const bool diag = B.diag && bb == B.a;
+        const bool bside = B.reuse && !diag;
+        int slot = 0;
+        bool cj = false;
+        if (diag) {
+            cj = jl < i;
+            slot = cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
+        } else {
+            slot = full_base + (bb - first_full) * nn + i * nocc + jl;
+        }
+        const cplx<T>* src = X + (size_t)slot * B.ng + plane_off;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int m2 = r0 + t * RPI;
+            if (m2 < NN) tile[m2 * LNP + lane] = active ? src[(size_t)m2 * NN] : mk<T>(T(0), T(0));
+        }
+        __syncthreads();
+        fft_lines<T, NN, +1, LNP, kPass3Threads>(tile, LNP, LNP, 1, tw + kMaxN);
+        const cplx<T>* pi = psi + ((size_t)bb * nocc + i) * B.ng + plane_off;
+        const cplx<T>* pa = psi + ((size_t)B.a * nocc + jl) * B.ng + plane_off;
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                const int n2 = r0 + t * RPI;
+                if (n2 < NN) {
+                    cplx<T> v = tile[n2 * LNP + lane];
+                    if (cj) v.y = -v.y;
+                    const cplx<T> u = pi[(size_t)n2 * NN];
+                    acc[t] = mk<T>(acc[t].x + u.x * v.x - u.y * v.y, acc[t].y + u.x * v.y + u.y * v.x);
+                    if (bside) {
+                        const cplx<T> o = pa[(size_t)n2 * NN];
+                        tile[n2 * LNP + lane] = mk<T>(o.x * v.x + o.y * v.y, o.y * v.x - o.x * v.y);  // o conj(v)
+                    }
+                }
+            }
+        }
+        if (bside) {
+            __syncthreads();
+            cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
+#pragma unroll
+            for (int t = 0; t < BPT; ++t) {
+                const int e = threadIdx.x + t * kPass3Threads;
+                if (e < BP) {
+                    const int n2 = e / WB, ww = e - n2 * WB;
+                    cplx<T> sum = wout[(size_t)n2 * NN + ww];
+                    for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, tile[n2 * LNP + j * WB + ww]);
+                    wout[(size_t)n2 * NN + ww] = sum;
+                }
+            }
+        }
+    }
+    if (active) {
+        cplx<T>* out = Wpart + ((size_t)s * nocc + jl) * B.ng + plane_off;
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int n2 = r0 + t * RPI;
+            if (n2 < NN) out[(size_t)n2 * NN] = acc[t];
+        }
     }
 }
 
@@ -277,31 +560,87 @@ size_t lds_plane_bytes(int rows, int cols) {
     return sizeof(cplx<T>) * (3 * kMaxN + (size_t)rows * (cols + 1));
 }
 
+// compile-time specialisations of cubic grids; 0 = sizes read at run time
+inline int specialised(const PairBatch& B) {
+    if (B.N1 != B.N2 || B.N2 != B.N3) return 0;
+    switch (B.N1) {
+        case 24: case 30: case 32: case 36: case 40: case 48: return B.N1;
+        default: return 0;
+    }
+}
+
+#define OCCRIK_DISPATCH(NNV, CALL)          \
+    switch (NNV) {                          \
+        case 24: { constexpr int NN = 24; CALL; } break; \
+        case 30: { constexpr int NN = 30; CALL; } break; \
+        case 32: { constexpr int NN = 32; CALL; } break; \
+        case 36: { constexpr int NN = 36; CALL; } break; \
+        case 40: { constexpr int NN = 40; CALL; } break; \
+        case 48: { constexpr int NN = 48; CALL; } break; \
+        default: { constexpr int NN = 0; CALL; } break;  \
+    }
+
 }  // namespace
+
+int pair_groups(const PairBatch& B) {
+    const int nn = B.nocc * B.nocc;
+    const int gd = B.diag ? (B.ntri + B.group - 1) / B.group : 0;
+    const int nfull = B.nb - (B.diag ? 1 : 0);
+    return gd + nfull * ((nn + B.group - 1) / B.group);
+}
 
 template <typename T>
 hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s) {
-    const unsigned grid = (unsigned)((size_t)B.N1 * B.nb * B.nocc * B.nocc);
-    hipLaunchKernelGGL(pass1_kernel<T>, dim3(grid), dim3(kFftThreads), lds_plane_bytes<T>(B.N2, B.N3), s, B, psi, X,
-                       tw);
+    const unsigned grid = (unsigned)((size_t)B.N1 * B.nslots);
+    const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
+    OCCRIK_DISPATCH(specialised(B),
+                    hipLaunchKernelGGL((pass1_kernel<T, NN>), dim3(grid), dim3(kFftThreads), lds, s, B, psi, X, tw));
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
                         hipStream_t s) {
-    const unsigned grid = (unsigned)((size_t)B.N2 * B.nb * B.nocc * B.nocc);
+    const unsigned grid = (unsigned)((size_t)B.N2 * pair_groups(B));
     const size_t lds = lds_plane_bytes<T>(B.N1, B.N3) + sizeof(double) * kFftThreads;
-    hipLaunchKernelGGL(pass2_kernel<T>, dim3(grid), dim3(kFftThreads), lds, s, B, X, tw, parts, deriv_only);
+    OCCRIK_DISPATCH(specialised(B), hipLaunchKernelGGL((pass2_kernel<T, NN>), dim3(grid), dim3(kFftThreads), lds, s,
+                                                       B, X, tw, parts, deriv_only));
     return hipGetLastError();
 }
 
+int pass3_splits(const PairBatch& B, int elem) {
+    const int target_wg = 2048;
+    const int nn = specialised(B);
+    const int base_wg = nn > 0 && B.nocc <= 16 ? nn * (nn / colblock(nn, elem)) : B.N1 * B.nocc;
+    return std::max(1, std::min(B.nb * B.nocc, (target_wg + base_wg - 1) / base_wg));
+}
+
 template <typename T>
-hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, const cplx<T>* tw,
-                        hipStream_t s) {
-    const unsigned grid = (unsigned)((size_t)B.N1 * B.nocc * B.splits);
-    hipLaunchKernelGGL(pass3_kernel<T>, dim3(grid), dim3(kFftThreads), lds_plane_bytes<T>(B.N2, B.N3), s, B, X, psi,
-                       Wpart, tw);
+hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
+                        const cplx<T>* tw, hipStream_t s) {
+    const int nnv = specialised(B);
+    if (nnv > 0 && B.nocc <= 16) {
+        const int wb = colblock(nnv, (int)sizeof(cplx<T>));
+        const unsigned grid = (unsigned)((size_t)nnv * (nnv / wb) * B.splits);
+        const int jc = B.nocc <= 8 ? 8 : 16;
+        int lnp = 1;
+        while (lnp < jc * wb) lnp *= 2;
+        const size_t lds = sizeof(cplx<T>) * (3 * kMaxN + (size_t)nnv * lnp);
+        if (jc == 8) {
+            OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 8>), dim3(grid),
+                                                                       dim3(kPass3Threads), lds, s, B, X, psi,
+                                                                       Wpart, W, tw));
+        } else {
+            OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 16>), dim3(grid),
+                                                                       dim3(kPass3Threads), lds, s, B, X, psi,
+                                                                       Wpart, W, tw));
+        }
+        return hipGetLastError();
+    }
+    const int nfull_b = B.reuse ? B.nb - (B.diag ? 1 : 0) : 0;
+    const unsigned grid = (unsigned)((size_t)B.N1 * B.nocc * B.splits + (size_t)nfull_b * B.nocc * B.N1);
+    const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
+    hipLaunchKernelGGL((pass3_kernel<T, 0>), dim3(grid), dim3(kFftThreads), lds, s, B, X, psi, Wpart, W, tw);
     return hipGetLastError();
 }
 
@@ -332,7 +671,7 @@ hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s) {
 #define OCCRIK_INST(T)                                                                                         \
     template hipError_t launch_pass1<T>(const PairBatch&, const cplx<T>*, cplx<T>*, const cplx<T>*, hipStream_t); \
     template hipError_t launch_pass2<T>(const PairBatch&, cplx<T>*, const cplx<T>*, double*, int, hipStream_t);   \
-    template hipError_t launch_pass3<T>(const PairBatch&, const cplx<T>*, const cplx<T>*, cplx<T>*,            \
+    template hipError_t launch_pass3<T>(const PairBatch&, const cplx<T>*, const cplx<T>*, cplx<T>*, cplx<T>*,  \
                                         const cplx<T>*, hipStream_t);                                           \
     template hipError_t launch_wreduce<T>(const PairBatch&, const cplx<T>*, cplx<T>*, hipStream_t);            \
     template hipError_t launch_fill_zero<T>(cplx<T>*, size_t, hipStream_t);

@@ -76,7 +76,7 @@ struct occrik_plan {
     std::vector<double> shell_exp;
     bool fp64 = true;
     size_t elem = 16;
-    int kbatch = 1, splits = 1, nchunks = 1;
+    int kbatch = 1, splits = 1, nchunks = 1, group = 8;
 
     // device memory
     std::vector<void*> allocations;
@@ -330,6 +330,18 @@ occrik_status make_twiddles(occrik_plan* P) {
     return OCCRIK_OK;
 }
 
+bool plan_reuses_pairs(const occrik_plan* P) { return P->params.nyquist == OCCRIK_NYQUIST_SYMMETRIC; }
+
+int splits_for(const occrik_plan* P, int nb) {
+    PairBatch B{};
+    B.N1 = P->N[0];
+    B.N2 = P->N[1];
+    B.N3 = P->N[2];
+    B.nocc = P->nocc;
+    B.nb = nb;
+    return pass3_splits(B, (int)P->elem);
+}
+
 PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     PairBatch B{};
     B.N1 = P->N[0];
@@ -343,12 +355,18 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     B.a = a;
     B.b0 = b0;
     B.nb = nb;
+    B.reuse = plan_reuses_pairs(P) ? 1 : 0;
+    B.diag = (B.reuse && b0 == a) ? 1 : 0;
+    B.ntri = P->nocc * (P->nocc + 1) / 2;
+    const int nn = P->nocc * P->nocc;
+    B.nslots = B.diag ? B.ntri + (nb - 1) * nn : nb * nn;
+    B.group = P->group;
     B.kernel = P->params.kernel;
     B.nyquist = P->params.nyquist;
     B.omega = P->params.omega;
     B.inv_ng = 1.0 / P->ng;
     std::memcpy(B.recip, P->recip, sizeof(B.recip));
-    B.splits = P->splits;
+    B.splits = splits_for(P, nb);
     B.parseval = 0;
     return B;
 }
@@ -374,8 +392,9 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
     OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
     int64_t launches = 1;
+    const bool reuse = plan_reuses_pairs(P);
     for (int a = 0; a < nk; ++a) {
-        for (int b0 = 0; b0 < nk; b0 += P->kbatch) {
+        for (int b0 = reuse ? a : 0; b0 < nk; b0 += P->kbatch) {
             const int nb = std::min(P->kbatch, nk - b0);
             PairBatch B = make_batch(P, a, b0, nb);
             hipEvent_t ev[4] = {};
@@ -384,7 +403,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
                     OCCRIK_HIP(hipEventCreate(&e));
                     pe.pe.push_back(e);
                 }
-                const double pb = double(nb) * nocc * nocc * ng * sizeof(cplx<T>);
+                const double pb = double(B.nslots) * ng * sizeof(cplx<T>);
                 pe.pbytes.push_back(pb);
                 pe.pbytes.push_back(2.0 * pb);
                 pe.pbytes.push_back(pb);
@@ -394,7 +413,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
             if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[1], s));
             OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 0, s));
             if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[2], s));
-            OCCRIK_HIP(launch_pass3<T>(B, X, psi, Wp, tw, s));
+            OCCRIK_HIP(launch_pass3<T>(B, X, psi, Wp, W, tw, s));
             OCCRIK_HIP(launch_wreduce<T>(B, Wp, W, s));
             if (P->profiling >= 2) OCCRIK_HIP(hipEventRecord(ev[3], s));
             launches += 4;
@@ -428,13 +447,14 @@ occrik_status domega_impl(occrik_plan* P, double* out_host) {
     const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(P->tw);
     OCCRIK_HIP(launch_fill_zero_f64(P->scal, 4, s));
     const double scale = -P->volume / (2.0 * double(nk) * nk * double(P->ng) * P->ng);
+    const bool reuse = plan_reuses_pairs(P);
     for (int a = 0; a < nk; ++a)
-        for (int b0 = 0; b0 < nk; b0 += P->kbatch) {
+        for (int b0 = reuse ? a : 0; b0 < nk; b0 += P->kbatch) {
             const int nb = std::min(P->kbatch, nk - b0);
             PairBatch B = make_batch(P, a, b0, nb);
             OCCRIK_HIP(launch_pass1<T>(B, psi, X, tw, s));
             OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 1, s));
-            OCCRIK_HIP(launch_sum_f64(P->parts, (size_t)nb * P->nocc * P->nocc * P->N[1], scale, P->scal, s));
+            OCCRIK_HIP(launch_sum_f64(P->parts, (size_t)pair_groups(B) * P->N[1], scale, P->scal, s));
         }
     OCCRIK_HIP(hipMemcpyAsync(out_host, P->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     OCCRIK_HIP(hipStreamSynchronize(s));
@@ -564,10 +584,11 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         const size_t cap = (size_t)16 << 30;
         P->kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_k));
     }
-    const int target_wg = 2048;
-    const int base_wg = P->N[0] * nocc;
-    P->splits = std::max(1, std::min(P->kbatch * nocc, (target_wg + base_wg - 1) / base_wg));
+    P->splits = splits_for(P, P->kbatch);
+    P->group = nocc;
     P->nchunks = std::max(1, std::min(64, ng / 4096));
+    const size_t max_groups = (size_t)P->kbatch * ((nocc * nocc + P->group - 1) / P->group) +
+                              (nocc * (nocc + 1) / 2 + P->group - 1) / P->group;
 
     hipError_t e = hipSuccess;
     auto A = [&](void** p, size_t bytes) {
@@ -580,7 +601,7 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     A(&P->X, (size_t)P->kbatch * per_k);
     A(&P->Wpart, (size_t)P->splits * nocc * ng * P->elem);
     A(&P->tw, 3 * kMaxN * P->elem);
-    A((void**)&P->parts, sizeof(double) * (size_t)P->kbatch * nocc * nocc * P->N[1]);
+    A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
     A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nocc * P->nchunks);
     A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nocc);
     A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nocc * nocc);
@@ -592,6 +613,11 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     if (e != hipSuccess) {
         delete P;
         return hip_fail(e, "plan allocation");
+    }
+    e = launch_reset_flags_n(P->flags, 2 + nk, P->stream);
+    if (e != hipSuccess) {
+        delete P;
+        return hip_fail(e, "flag initialisation");
     }
     st = P->fp64 ? make_twiddles<double>(P) : make_twiddles<float>(P);
     if (st == OCCRIK_OK) st = P->fp64 ? run_collocation<double>(P) : run_collocation<float>(P);
@@ -629,7 +655,10 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
     info->cell_volume = P->volume;
     info->bytes_chi = P->bytes_chi;
     info->bytes_workspace = P->bytes_alloc - P->bytes_chi;
-    info->pair_transforms = (int64_t)P->nk * P->nk * P->nocc * P->nocc;
+    info->pair_transforms = plan_reuses_pairs(P)
+                                ? (int64_t)P->nk * (P->nk - 1) / 2 * P->nocc * P->nocc +
+                                      (int64_t)P->nk * P->nocc * (P->nocc + 1) / 2
+                                : (int64_t)P->nk * P->nk * P->nocc * P->nocc;
     info->plan_seconds = P->plan_seconds;
     return OCCRIK_OK;
 }
@@ -657,6 +686,7 @@ occrik_status occrik_build_device(occrik_plan* P, const void* dC, void* dK, void
 
 occrik_status occrik_plan_status(occrik_plan* P) {
     if (!P) return fail(OCCRIK_ERR_INVALID_ARG, "null plan");
+    if (!P->built) return OCCRIK_OK;
     DeviceGuard guard(P->device);
     int h[2];
     OCCRIK_HIP(hipMemcpyAsync(h, P->flags, sizeof(h), hipMemcpyDeviceToHost, P->stream));

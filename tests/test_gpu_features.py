@@ -1,0 +1,205 @@
+"""GPU tests of the reduced-precision modes, the adjoint, error paths, invariants
+and the ragged batch entry point, all through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import collocation, occrik
+import paper_2207_09028_amd as pkg
+from paper_2207_09028_amd import OccrikError
+from paper_2207_09028_amd.autograd import exchange_energy
+from paper_2207_09028_amd.plan import Plan, PlanSpec, build_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu_required():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+_cache = {}
+
+
+def ref_for(prob, C, nyquist="symmetric", domega=False):
+    key = (prob.name, prob.grid, prob.kmesh, prob.nocc, prob.kernel, prob.omega, nyquist, prob.seed, domega)
+    if key not in _cache:
+        chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+        _cache[key] = occrik.build(prob, C, chi=chi, nyquist=nyquist, domega=domega)
+    return _cache[key]
+
+
+# ----------------------------------------------------------------------------
+# reduced precision
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [pkg.PREC_FP32, pkg.PREC_FP32_SPLIT])
+@pytest.mark.parametrize("name", ["tiny", "small"])
+def test_reduced_precision_meets_the_accuracy_gate(prec, name):
+    """|dE_x| <= 1e-6 E_h and max|dK~| <= 1e-5 against the FP64 oracle."""
+    prob = W.make_problem(name) if name != "small" else W.small_problem()
+    C = W.random_coefficients(prob)
+    ref = ref_for(prob, C)
+    plan = Plan(PlanSpec.from_problem(prob, precision=prec))
+    out = plan.build(torch.from_numpy(C).to("cuda"))
+    dE = abs(float(out["Ex"][0]) - ref["Ex"])
+    dK = float(np.max(np.abs(out["K"].cpu().numpy() - ref["K"])))
+    print(name, prec, "dEx", dE, "max dK", dK)
+    assert dE <= 1e-6
+    assert dK <= 1e-5
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+# ----------------------------------------------------------------------------
+
+def test_gradient_in_C_is_2K_over_Nk_and_matches_finite_differences():
+    prob = W.small_problem()
+    C = W.random_coefficients(prob)
+    ref = ref_for(prob, C)
+    plan = Plan(PlanSpec.from_problem(prob))
+    Ct = torch.from_numpy(C).to("cuda")
+    plan.build(Ct)
+    g, _ = plan.grad(1.0, want_C=True)
+    g = g.cpu().numpy()
+    assert rel(g, occrik.energy_gradient_C(ref["Kmi"], prob.nk)) < 1e-10
+    rng = np.random.default_rng(7)
+    h = 1e-5
+    for _ in range(4):
+        k, mu, i = int(rng.integers(prob.nk)), int(rng.integers(prob.nao)), int(rng.integers(prob.nocc))
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            Cp = C.copy(); Cp[k, mu, i] += h * unit
+            Cm = C.copy(); Cm[k, mu, i] -= h * unit
+            ep = float(plan.build(torch.from_numpy(Cp).to("cuda"), want_K=False)["Ex"][0])
+            em = float(plan.build(torch.from_numpy(Cm).to("cuda"), want_K=False)["Ex"][0])
+            fd = (ep - em) / (2 * h)
+            an = g[k, mu, i].real if part == "re" else g[k, mu, i].imag
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an)) + 1e-9
+
+
+def test_gradient_in_omega_matches_oracle_and_finite_differences():
+    prob = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.3)
+    C = W.random_coefficients(prob)
+    ref = ref_for(prob, C, domega=True)
+    plan = Plan(PlanSpec.from_problem(prob))
+    Ct = torch.from_numpy(C).to("cuda")
+    plan.build(Ct, want_K=False)
+    _, dw = plan.grad(1.0, want_C=False, want_omega=True)
+    assert abs(dw - ref["dEx_domega"]) < 1e-10 * abs(ref["dEx_domega"])
+    h = 1e-4
+    plan.set_omega(0.3 + h)
+    ep = float(plan.build(Ct, want_K=False)["Ex"][0])
+    plan.set_omega(0.3 - h)
+    em = float(plan.build(Ct, want_K=False)["Ex"][0])
+    assert abs((ep - em) / (2 * h) - dw) < 1e-7 * abs(dw)
+
+
+def test_autograd_function_backward():
+    prob = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.35)
+    C = W.random_coefficients(prob)
+    plan = Plan(PlanSpec.from_problem(prob))
+    Ct = torch.from_numpy(C).to("cuda").requires_grad_(True)
+    w = torch.tensor(0.35, dtype=torch.float64, requires_grad=True)
+    E = exchange_energy(plan, Ct, w)
+    (3.0 * E).backward()
+    ref = ref_for(prob, C, domega=True)
+    assert abs(float(E) - ref["Ex"]) < 1e-10 * abs(ref["Ex"])
+    assert rel(Ct.grad.cpu().numpy(), 3.0 * occrik.energy_gradient_C(ref["Kmi"], prob.nk)) < 1e-10
+    assert abs(float(w.grad) - 3.0 * ref["dEx_domega"]) < 1e-10 * abs(3.0 * ref["dEx_domega"])
+
+
+def test_grad_before_build_is_a_state_error():
+    prob = W.small_problem()
+    plan = Plan(PlanSpec.from_problem(prob))
+    with pytest.raises(OccrikError) as e:
+        plan.grad(1.0)
+    assert e.value.status == 7
+
+
+# ----------------------------------------------------------------------------
+# invariants
+# ----------------------------------------------------------------------------
+
+def test_invariants_on_gpu_outputs():
+    prob = W.make_problem("tiny")
+    C = W.random_coefficients(prob)
+    plan = Plan(PlanSpec.from_problem(prob))
+    out = plan.build(torch.from_numpy(C).to("cuda"))
+    K = out["K"].cpu().numpy()
+    Kmi = out["Kmi"].cpu().numpy()
+    assert np.max(np.abs(K - K.conj().transpose(0, 2, 1))) < 1e-13 * np.max(np.abs(K))
+    assert rel(np.einsum("kab,kbi->kai", K, C), Kmi) < 1e-11
+    # gauge invariance: C -> C U_k leaves K~ and E_x unchanged
+    rng = np.random.default_rng(5)
+    U = np.stack([np.linalg.qr(rng.standard_normal((prob.nocc, prob.nocc)) +
+                               1j * rng.standard_normal((prob.nocc, prob.nocc)))[0] for _ in range(prob.nk)])
+    C2 = np.einsum("kmi,kij->kmj", C, U)
+    out2 = plan.build(torch.from_numpy(C2).to("cuda"))
+    assert rel(out2["K"].cpu().numpy(), K) < 1e-11
+    assert abs(float(out2["Ex"][0]) - float(out["Ex"][0])) < 1e-12 * abs(float(out["Ex"][0]))
+
+
+# ----------------------------------------------------------------------------
+# error paths (forced from the host; every kernel still exits normally)
+# ----------------------------------------------------------------------------
+
+def test_singular_occupied_block_reports_not_pd_with_k():
+    prob = W.small_problem()
+    C = W.random_coefficients(prob)
+    C[3, :, 1] = 0.0                             # empty orbital at k = 3: K_ij(3) has a zero row and column
+    plan = Plan(PlanSpec.from_problem(prob))
+    with pytest.raises(OccrikError) as e:
+        plan.build(torch.from_numpy(C).to("cuda"))
+    assert e.value.status == 4 and e.value.k == 3
+    # the plan stays usable
+    C2 = W.random_coefficients(prob)
+    plan.build(torch.from_numpy(C2).to("cuda"))
+
+
+def test_nonfinite_coefficients_are_reported():
+    prob = W.small_problem()
+    C = W.random_coefficients(prob)
+    C[1, 2, 0] = np.nan
+    plan = Plan(PlanSpec.from_problem(prob))
+    with pytest.raises(OccrikError) as e:
+        plan.build(torch.from_numpy(C).to("cuda"))
+    assert e.value.status == 5
+    with pytest.raises(OccrikError) as e:
+        plan.build_host(C)
+    assert e.value.status == 5
+
+
+def test_memory_budget_too_small_reports_oom():
+    prob = W.small_problem()
+    with pytest.raises(OccrikError) as e:
+        Plan(PlanSpec.from_problem(prob, mem_budget=1 << 16))
+    assert e.value.status == 3
+
+
+# ----------------------------------------------------------------------------
+# ragged batch
+# ----------------------------------------------------------------------------
+
+def test_ragged_batch_equals_single_builds_bitwise():
+    probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
+             W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=2, counts=(1, 1, 1), seed=2),
+             W.small_problem(kmesh=(2, 2, 1), grid=(24, 24, 24), nocc=4, counts=(2, 2, 1), seed=3)]
+    plans, Cs, Ks, Es, singles = [], [], [], [], []
+    for p in probs:
+        C = W.random_coefficients(p)
+        plan = Plan(PlanSpec.from_problem(p, precision=pkg.PREC_FP32))
+        Ct = torch.from_numpy(C).to("cuda")
+        singles.append(plan.build(Ct))
+        plans.append(plan)
+        Cs.append(Ct)
+        Ks.append(torch.empty_like(singles[-1]["K"]))
+        Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+    build_batch(plans, Cs, Ks=Ks, Exs=Es)
+    torch.cuda.synchronize()
+    for s, K, E in zip(singles, Ks, Es):
+        assert torch.equal(s["K"], K) and torch.equal(s["Ex"], E)

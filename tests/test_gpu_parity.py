@@ -139,3 +139,46 @@ def test_host_entry_point_matches_device_entry_point():
     d = plan.build(torch.from_numpy(C).to("cuda"))
     assert np.array_equal(h["K"], d["K"].cpu().numpy())
     assert h["Ex"] == float(d["Ex"][0])
+
+
+def test_status_before_any_build_is_ok():
+    prob = W.small_problem()
+    plan = Plan(PlanSpec.from_problem(prob))
+    plan.status()
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny14"])
+def test_specialised_grid_kernels_match_oracle_in_both_modes(name):
+    """24^3 runs the compile-time-size pass kernels; both Nyquist modes (with and without pair reuse)."""
+    prob = W.make_problem(name)
+    C = W.random_coefficients(prob)
+    for mode in ("fftfreq", "symmetric"):
+        ref = oracle_result(prob, C, mode)
+        _, out = run_gpu(prob, C, mode)
+        assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+        assert rel(out["K"], ref["K"]) < TOL64
+        assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+
+
+def test_pair_reuse_with_split_rows():
+    """Symmetric mode with kbatch < N_k: rows of the upper triangle split across batches."""
+    prob = W.small_problem(kmesh=(2, 2, 2), grid=(10, 9, 8), nocc=3)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, "symmetric")
+    for kb in (1, 3, 5):
+        _, out = run_gpu(prob, C, "symmetric", kbatch=kb)
+        assert rel(out["Kmi"], ref["Kmi"]) < TOL64, kb
+        assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+
+
+@pytest.mark.parametrize("nocc,kbatch,mode", [(10, 0, "symmetric"), (3, 3, "symmetric"), (5, 2, "fftfreq"),
+                                              (8, 0, "fftfreq")])
+def test_fused_pass3_variants_on_a_specialised_grid(nocc, kbatch, mode):
+    """24^3 grid: the fused pass 3 with 8 or 16 orbital lanes, split rows and both Nyquist modes."""
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=nocc, counts=(2, 2, 1), seed=21 + nocc)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, mode)
+    _, out = run_gpu(prob, C, mode, kbatch=kbatch)
+    assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+    assert rel(out["K"], ref["K"]) < TOL64
+    assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
