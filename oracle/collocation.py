@@ -121,3 +121,38 @@ def ao_labels(basis):
         for ic in range(len(cartesian_powers(int(l)))):
             out.append((s, ic))
     return out
+
+
+def occupied_orbitals_streamed(cell, basis, kmesh, grid, C, tol=1e-12, chunk=1024):
+    """psi[k, i, n] = sum_mu C[k, mu, i] chi[k, mu, n] (paper eq. occmo) without
+    holding chi for every k: chi is formed for a slab of grid points at a time
+    (the same Bloch sums as ``collocate``) and contracted with C at once."""
+    lattice = cell.lattice
+    kf = lat_mod.kpoints_fractional(kmesh)
+    r = lat_mod.grid_points(lattice, grid)
+    ng = r.shape[0]
+    centers = cell.atoms_frac @ lattice
+    nk, nao, nocc = C.shape
+    psi = np.zeros((nk, nocc, ng), dtype=np.complex128)
+    shells = []
+    for s in range(len(basis.shell_l)):
+        l = int(basis.shell_l[s])
+        alpha = float(basis.shell_exp[s])
+        R = centers[int(basis.shell_atom[s])]
+        t = shell_images(lattice, R, alpha, l, tol)
+        powers = cartesian_powers(l)
+        shells.append((l, alpha, R, t @ lattice, np.exp(2j * np.pi * (kf @ t.T)), powers,
+                       [component_norm(alpha, *p) for p in powers]))
+    for n0 in range(0, ng, chunk):
+        rc = r[n0:n0 + chunk]
+        chi = np.empty((nk, nao, rc.shape[0]), dtype=np.complex128)
+        mu0 = 0
+        for (l, alpha, R, T, phase, powers, norms) in shells:
+            x = rc[None, :, :] - R[None, None, :] - T[:, None, :]
+            radial = np.exp(-alpha * np.sum(x * x, axis=2))
+            for ic, (a, b, c) in enumerate(powers):
+                phi = norms[ic] * x[..., 0] ** a * x[..., 1] ** b * x[..., 2] ** c * radial
+                chi[:, mu0 + ic, :] = phase @ phi
+            mu0 += len(powers)
+        psi[:, :, n0:n0 + chunk] = np.matmul(C.transpose(0, 2, 1), chi)
+    return psi

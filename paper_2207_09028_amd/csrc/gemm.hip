@@ -1,112 +1,296 @@
-// The two grid contractions of the build.
+// The two grid contractions of the build, on the matrix cores.
 //
 //   orbitals   psi~_{j k}(r) = sum_mu C_{mu j}(k) chi~_{mu k}(r)           (paper eq. occmo)
 //   contract   K_{mu j}(k)   = -(dV/N_k) sum_r conj(chi~_{mu k}(r)) W~_{j k}(r)
 //                                                      (the contraction of Alg. 3)
 //
-// Both stream the Bloch AOs on the grid (N_k x N_ao x N_g) once and are
-// bandwidth-bound for the few occupied columns involved.  The contraction
-// splits the grid sum into fixed chunks, keeps each chunk's sum in the working
-// precision, and adds the chunk partials in FP64 in a fixed order.
+// Both are written as real GEMMs over interleaved (re, im) data:
+//   orbitals   D[2j + c][n]  = sum_{2mu + c'} A[2j + c][2mu + c'] chi_{c'}(mu, n),
+//              A = [[Re C, -Im C], [Im C, Re C]] per (j, mu)
+//   contract   D[mu][2j + c'] = sum_{2n + c} chi_c(mu, n) B[2n + c][2j + c'],
+//              B = [[Re W, Im W], [Im W, -Re W]] per (n, j)
+// and run as 16 x 16 MFMA tiles:
+//   MODE 0  FP64 data, v_mfma_f64_16x16x4_f64
+//   MODE 1  FP32 data, v_mfma_f32_16x16x4_f32
+//   MODE 2  FP32 data split into three bf16 terms x = h + m + l per operand,
+//           v_mfma_f32_16x16x32_bf16 on the six products hh, hm, mh, hl, lh, mm
+//           with FP32 accumulation (the 3-term splitting of Henry, Tang and
+//           Heinecke, ARITH 2019).
+// Lane layouts (16x16xK): A[i][k] in lane i%16 + 16 * (k / KL), B[k][j] in lane
+// j + 16 * (k / KL), where KL is the number of k values a lane holds (1 for x4,
+// 8 for x32).  D[i][j] sits in lane j + 16 * (i / 4), register i % 4 for the
+// FP32-output forms, and in lane j + 16 * (i % 4), register i / 4 for the FP64
+// form (both checked on the device with one-hot operands).
+//
+// The contraction splits the grid sum into chunks; each chunk is accumulated
+// in the working precision and the chunk partials are added in FP64 in a fixed
+// order.  Both kernels stream the Bloch AOs once and are bandwidth-bound for
+// the few occupied columns involved.
 #include "internal.hpp"
 
 namespace occrik {
 
 namespace {
 
-constexpr int kMaxOcc = 16;
-constexpr int kCChunk = 128;     // AOs of C staged in LDS at a time
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-template <typename T>
-__global__ void __launch_bounds__(256) orbitals_kernel(const cplx<T>* __restrict__ chi, const double2* __restrict__ C,
-                                                       cplx<T>* __restrict__ psi, int nao, int nocc, int ng) {
-    __shared__ cplx<T> cs[kCChunk * kMaxOcc];
-    const int k = blockIdx.y;
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    cplx<T> acc[kMaxOcc];
+template <int MODE> struct Acc { typedef f4 type; };
+template <> struct Acc<0> { typedef d4 type; };
+
+// row of D held by lane l in accumulator register r
+template <int MODE>
+__device__ __forceinline__ int out_row(int l, int r) {
+    return MODE == 0 ? 4 * r + (l >> 4) : 4 * (l >> 4) + r;
+}
+
+// three-term bf16 splitting of an FP32 value
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+    h = (__bf16)x;
+    const float r1 = x - (float)h;
+    m = (__bf16)r1;
+    l = (__bf16)(r1 - (float)m);
+}
+
+template <int MODE>
+__device__ __forceinline__ typename Acc<MODE>::type mfma4(double a, double b, typename Acc<MODE>::type c);
+template <>
+__device__ __forceinline__ d4 mfma4<0>(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ f4 mfma4<1>(double a, double b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+}
+
+// six-product split-bf16 step over 8 k values per lane
+__device__ __forceinline__ f4 mfma_split(const float* a, const float* b, f4 c) {
+    bf8 ah, am, al, bh, bm, bl;
 #pragma unroll
-    for (int j = 0; j < kMaxOcc; ++j) acc[j] = mk<T>(T(0), T(0));
+    for (int v = 0; v < 8; ++v) {
+        __bf16 h, m, l;
+        split3(a[v], h, m, l);
+        ah[v] = h; am[v] = m; al[v] = l;
+        split3(b[v], h, m, l);
+        bh[v] = h; bm[v] = m; bl[v] = l;
+    }
+    // small terms first
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    return c;
+}
+
+constexpr int kMaxRowTiles = 2;   // 2 nocc <= 32
+constexpr int kOrbChunk = 32;     // AOs per LDS chunk of the A operand
+constexpr int kOrbTiles = 4;      // 16-point tiles per wave
+constexpr int kFlush = 32;        // FP32 MFMA steps (x4 forms) between FP64 flushes in the contraction
+
+// ---------------------------------------------------------------------------
+// orbitals: one workgroup = 4 waves x 4 tiles x 16 points of one k
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__ chi, const double2* __restrict__ C,
+                                                     cplx<T>* __restrict__ psi, int nao, int nocc, int ng) {
+    typedef typename Acc<MODE>::type acc_t;
+    constexpr int KCH = 2 * kOrbChunk;                  // real k values per chunk
+    __shared__ T alds[kMaxRowTiles][16][KCH];
+    const int k = blockIdx.y;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int nbase = (blockIdx.x * 4 + wave) * kOrbTiles * 16;
+    const int rt_n = (2 * nocc + 15) / 16;
+    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * k * nao * ng;
     const double2* Ck = C + (size_t)k * nao * nocc;
-    const cplx<T>* ck = chi + (size_t)k * nao * ng;
-    for (int m0 = 0; m0 < nao; m0 += kCChunk) {
-        const int mc = min(kCChunk, nao - m0);
+    acc_t acc[kMaxRowTiles][kOrbTiles];
+#pragma unroll
+    for (int rt = 0; rt < kMaxRowTiles; ++rt)
+#pragma unroll
+        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = acc_t{};
+    for (int m0 = 0; m0 < nao; m0 += kOrbChunk) {
         __syncthreads();
-        for (int t = threadIdx.x; t < mc * nocc; t += 256) {
-            const double2 c = Ck[(size_t)m0 * nocc + t];
-            cs[t] = mk<T>(T(c.x), T(c.y));
+        for (int idx = threadIdx.x; idx < kMaxRowTiles * 16 * KCH; idx += 256) {
+            const int rt = idx / (16 * KCH), rem = idx - rt * 16 * KCH, row = rem / KCH, kk = rem - row * KCH;
+            const int j = (rt * 16 + row) >> 1, c = row & 1, mu = m0 + (kk >> 1), cc = kk & 1;
+            T a = T(0);
+            if (j < nocc && mu < nao) {
+                const double2 cv = Ck[(size_t)mu * nocc + j];
+                a = T(c == 0 ? (cc == 0 ? cv.x : -cv.y) : (cc == 0 ? cv.y : cv.x));
+            }
+            alds[rt][row][kk] = a;
         }
         __syncthreads();
-        if (n < ng) {
-            for (int m = 0; m < mc; ++m) {
-                const cplx<T> x = ck[(size_t)(m0 + m) * ng + n];
+        if constexpr (MODE < 2) {
+#pragma unroll 4
+            for (int s = 0; s < KCH / 4; ++s) {
+                const int kk = 4 * s + (l >> 4);
+                const int mu = m0 + (kk >> 1), cc = kk & 1;
+                T bv[kOrbTiles];
 #pragma unroll
-                for (int j = 0; j < kMaxOcc; ++j) {
-                    if (j < nocc) {
-                        const cplx<T> c = cs[m * nocc + j];
-                        acc[j] = mk<T>(acc[j].x + c.x * x.x - c.y * x.y, acc[j].y + c.x * x.y + c.y * x.x);
+                for (int t = 0; t < kOrbTiles; ++t) {
+                    const int n = nbase + 16 * t + (l & 15);
+                    bv[t] = (mu < nao && n < ng) ? chir[2 * ((size_t)mu * ng + n) + cc] : T(0);
+                }
+#pragma unroll
+                for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+                    if (rt < rt_n) {
+                        const T a = alds[rt][l & 15][kk];
+#pragma unroll
+                        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = mfma4<MODE>(a, bv[t], acc[rt][t]);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < KCH / 32; ++s) {
+                const int kk0 = 32 * s + 8 * (l >> 4);
+                float bv[kOrbTiles][8];
+#pragma unroll
+                for (int t = 0; t < kOrbTiles; ++t) {
+                    const int n = nbase + 16 * t + (l & 15);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int kk = kk0 + v, mu = m0 + (kk >> 1), cc = kk & 1;
+                        bv[t][v] = (mu < nao && n < ng) ? (float)chir[2 * ((size_t)mu * ng + n) + cc] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+                    if (rt < rt_n) {
+                        float av[8];
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) av[v] = (float)alds[rt][l & 15][kk0 + v];
+#pragma unroll
+                        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = mfma_split(av, bv[t], acc[rt][t]);
                     }
                 }
             }
         }
     }
-    if (n < ng) {
+    T* psir = reinterpret_cast<T*>(psi) + (size_t)2 * k * nocc * ng;
 #pragma unroll
-        for (int j = 0; j < kMaxOcc; ++j)
-            if (j < nocc) psi[((size_t)k * nocc + j) * ng + n] = acc[j];
+    for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+        if (rt >= rt_n) continue;
+#pragma unroll
+        for (int t = 0; t < kOrbTiles; ++t) {
+            const int n = nbase + 16 * t + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + out_row<MODE>(l, r), j = row >> 1, c = row & 1;
+                if (j < nocc && n < ng) psir[2 * ((size_t)j * ng + n) + c] = T(acc[rt][t][r]);
+            }
+        }
     }
 }
 
-// One wave per AO, 4 AOs per workgroup, a chunk of grid points per workgroup.
-template <typename T>
-__global__ void __launch_bounds__(256) contract_kernel(const cplx<T>* __restrict__ chi, const cplx<T>* __restrict__ W,
-                                                       double2* __restrict__ Kpart, int nao, int nocc, int ng,
-                                                       int chunk) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = blockIdx.x;
-    const int mu = blockIdx.y * 4 + wave;
+// ---------------------------------------------------------------------------
+// contraction: one wave = 16 AOs x (2 nocc) columns over one chunk of the grid
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__ chi, const cplx<T>* __restrict__ W,
+                                                     double* __restrict__ Kpart, int nao, int nocc, int ng,
+                                                     int chunk) {
+    typedef typename Acc<MODE>::type acc_t;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int c = blockIdx.x, nchunks = gridDim.x;
+    const int mu0 = (blockIdx.y * 4 + wave) * 16;
     const int k = blockIdx.z;
-    const int nchunks = gridDim.x;
-    const int n0 = c * chunk;
-    const int n1 = min(ng, n0 + chunk);
-    cplx<T> acc[kMaxOcc];
+    const int n0 = c * chunk, n1 = min(ng, n0 + chunk);
+    const int ct_n = (2 * nocc + 15) / 16;
+    const int mu = mu0 + (l & 15);
+    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * ((size_t)k * nao + min(mu, nao - 1)) * ng;
+    const cplx<T>* Wk = W + (size_t)k * nocc * ng;
+    acc_t acc[kMaxRowTiles];
+    double tot[kMaxRowTiles][4];
 #pragma unroll
-    for (int j = 0; j < kMaxOcc; ++j) acc[j] = mk<T>(T(0), T(0));
-    if (mu < nao) {
-        const cplx<T>* x = chi + ((size_t)k * nao + mu) * ng;
-        const cplx<T>* w = W + (size_t)k * nocc * ng;
-        for (int n = n0 + lane; n < n1; n += 64) {
-            const cplx<T> xv = x[n];
+    for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+        acc[rt] = acc_t{};
 #pragma unroll
-            for (int j = 0; j < kMaxOcc; ++j) {
-                if (j < nocc) {
-                    const cplx<T> wv = w[(size_t)j * ng + n];
-                    acc[j] = mk<T>(acc[j].x + xv.x * wv.x + xv.y * wv.y, acc[j].y + xv.x * wv.y - xv.y * wv.x);
+        for (int r = 0; r < 4; ++r) tot[rt][r] = 0.0;
+    }
+    // FP32 accumulators are flushed into FP64 running sums every kFlush steps
+    auto flush = [&]() {
+#pragma unroll
+        for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[rt][r] += double(acc[rt][r]);
+            acc[rt] = acc_t{};
+        }
+    };
+    if (mu0 < nao) {
+        if constexpr (MODE < 2) {
+            // 4 real k values per step = 2 grid points
+            int step = 0;
+            for (int n = n0; n < n1; n += 2) {
+                const int nn = n + ((l >> 4) >> 1), cc = (l >> 4) & 1;
+                const bool ok = nn < n1;
+                const T a = (ok && mu < nao) ? chir[2 * (size_t)nn + cc] : T(0);
+#pragma unroll
+                for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+                    if (rt < ct_n) {
+                        const int col = rt * 16 + (l & 15), j = col >> 1, cp = col & 1;
+                        T b = T(0);
+                        if (ok && j < nocc) {
+                            const cplx<T> w = Wk[(size_t)j * ng + nn];
+                            b = cp == 0 ? (cc == 0 ? w.x : w.y) : (cc == 0 ? w.y : -w.x);
+                        }
+                        acc[rt] = mfma4<MODE>(a, b, acc[rt]);
+                    }
+                }
+                if constexpr (MODE == 1) {
+                    if (++step == kFlush) {
+                        flush();
+                        step = 0;
+                    }
+                }
+            }
+        } else {
+            // 32 real k values per step = 16 grid points; this lane holds 4 consecutive points
+            int step = 0;
+            for (int n = n0; n < n1; n += 16) {
+                const int nb = n + 4 * (l >> 4);
+                float av[8];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const bool ok = nb + p < n1 && mu < nao;
+                    av[2 * p] = ok ? (float)chir[2 * (size_t)(nb + p)] : 0.f;
+                    av[2 * p + 1] = ok ? (float)chir[2 * (size_t)(nb + p) + 1] : 0.f;
+                }
+#pragma unroll
+                for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+                    if (rt < ct_n) {
+                        const int col = rt * 16 + (l & 15), j = col >> 1, cp = col & 1;
+                        float bv[8];
+#pragma unroll
+                        for (int p = 0; p < 4; ++p) {
+                            cplx<T> w = mk<T>(T(0), T(0));
+                            if (nb + p < n1 && j < nocc) w = Wk[(size_t)j * ng + nb + p];
+                            bv[2 * p] = cp == 0 ? (float)w.x : (float)w.y;
+                            bv[2 * p + 1] = cp == 0 ? (float)w.y : -(float)w.x;
+                        }
+                        acc[rt] = mfma_split(av, bv, acc[rt]);
+                    }
+                }
+                if (++step == kFlush / 8) {
+                    flush();
+                    step = 0;
                 }
             }
         }
     }
-    // wave reduction in FP64 of the per-lane partials (fixed order)
-    __shared__ double red[4][64][2];
+    flush();
 #pragma unroll
-    for (int j = 0; j < kMaxOcc; ++j) {
-        if (j >= nocc) break;
-        red[wave][lane][0] = double(acc[j].x);
-        red[wave][lane][1] = double(acc[j].y);
-        __syncthreads();
-        for (int w2 = 32; w2 > 0; w2 >>= 1) {
-            if (lane < w2) {
-                red[wave][lane][0] += red[wave][lane + w2][0];
-                red[wave][lane][1] += red[wave][lane + w2][1];
-            }
-            __syncthreads();
+    for (int rt = 0; rt < kMaxRowTiles; ++rt) {
+        if (rt >= ct_n) continue;
+        const int col = rt * 16 + (l & 15), j = col >> 1, cp = col & 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = mu0 + out_row<MODE>(l, r);
+            if (m < nao && j < nocc) Kpart[2 * ((((size_t)k * nao + m) * nocc + j) * nchunks + c) + cp] = tot[rt][r];
         }
-        if (lane == 0 && mu < nao) {
-            double2 r;
-            r.x = red[wave][0][0];
-            r.y = red[wave][0][1];
-            Kpart[(((size_t)k * nao + mu) * nocc + j) * nchunks + c] = r;
-        }
-        __syncthreads();
     }
 }
 
@@ -130,18 +314,31 @@ __global__ void contract_reduce_kernel(const double2* __restrict__ Kpart, double
 
 template <typename T>
 hipError_t launch_orbitals(const cplx<T>* chi, const double2* C, cplx<T>* psi, int nk, int nao, int nocc, int ng,
-                           hipStream_t s) {
-    dim3 grid((unsigned)((ng + 255) / 256), (unsigned)nk);
-    hipLaunchKernelGGL(orbitals_kernel<T>, grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+                           int mode, hipStream_t s) {
+    const int per_wg = 4 * kOrbTiles * 16;
+    dim3 grid((unsigned)((ng + per_wg - 1) / per_wg), (unsigned)nk);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((orbitals_mfma<T, 0>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+    } else {
+        if (mode == 2) hipLaunchKernelGGL((orbitals_mfma<T, 2>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+        else hipLaunchKernelGGL((orbitals_mfma<T, 1>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart, double2* Kmi, int nk, int nao,
-                           int nocc, int ng, int nchunks, double scale, hipStream_t s) {
-    const int chunk = (ng + nchunks - 1) / nchunks;
-    dim3 grid((unsigned)nchunks, (unsigned)((nao + 3) / 4), (unsigned)nk);
-    hipLaunchKernelGGL(contract_kernel<T>, grid, dim3(256), 0, s, chi, W, Kpart, nao, nocc, ng, chunk);
+                           int nocc, int ng, int nchunks, double scale, int mode, hipStream_t s) {
+    int chunk = (ng + nchunks - 1) / nchunks;
+    chunk = (chunk + 15) / 16 * 16;
+    dim3 grid((unsigned)nchunks, (unsigned)((nao + 63) / 64), (unsigned)nk);
+    double* kp = reinterpret_cast<double*>(Kpart);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((contract_mfma<T, 0>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
+    } else {
+        if (mode == 2) hipLaunchKernelGGL((contract_mfma<T, 2>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
+        else hipLaunchKernelGGL((contract_mfma<T, 1>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t n = (size_t)nk * nao * nocc;
@@ -150,13 +347,13 @@ hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart,
     return hipGetLastError();
 }
 
-template hipError_t launch_orbitals<float>(const cplx<float>*, const double2*, cplx<float>*, int, int, int, int,
+template hipError_t launch_orbitals<float>(const cplx<float>*, const double2*, cplx<float>*, int, int, int, int, int,
                                            hipStream_t);
 template hipError_t launch_orbitals<double>(const cplx<double>*, const double2*, cplx<double>*, int, int, int, int,
-                                            hipStream_t);
+                                            int, hipStream_t);
 template hipError_t launch_contract<float>(const cplx<float>*, const cplx<float>*, double2*, double2*, int, int, int,
-                                           int, int, double, hipStream_t);
+                                           int, int, double, int, hipStream_t);
 template hipError_t launch_contract<double>(const cplx<double>*, const cplx<double>*, double2*, double2*, int, int,
-                                            int, int, int, double, hipStream_t);
+                                            int, int, int, double, int, hipStream_t);
 
 }  // namespace occrik

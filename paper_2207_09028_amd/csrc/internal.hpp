@@ -58,12 +58,13 @@ template <typename T>
 hipError_t launch_fill_zero(cplx<T>* p, size_t n, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s);
 
+// Grid contractions on the matrix cores; mode = OCCRIK_PREC_* (FP32_SPLIT uses split-bf16).
 template <typename T>
 hipError_t launch_orbitals(const cplx<T>* chi, const double2* C, cplx<T>* psi, int nk, int nao, int nocc, int ng,
-                           hipStream_t s);
+                           int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart, double2* Kmi, int nk, int nao,
-                           int nocc, int ng, int nchunks, double scale, hipStream_t s);
+                           int nocc, int ng, int nchunks, double scale, int mode, hipStream_t s);
 
 // Assembly (FP64).
 hipError_t launch_check_finite(const double2* C, size_t n, int* flags, hipStream_t s);

@@ -388,7 +388,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     }
     OCCRIK_HIP(launch_reset_flags_n(P->flags, 2 + nk, s));
     OCCRIK_HIP(launch_check_finite(dC, (size_t)nk * nao * nocc, P->flags, s));
-    OCCRIK_HIP(launch_orbitals<T>(chi, dC, psi, nk, nao, nocc, ng, s));
+    OCCRIK_HIP(launch_orbitals<T>(chi, dC, psi, nk, nao, nocc, ng, P->params.precision, s));
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
     OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
     int64_t launches = 1;
@@ -420,7 +420,8 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
         }
     }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[2], s));
-    OCCRIK_HIP(launch_contract<T>(chi, W, P->Kpart, P->Kmi, nk, nao, nocc, ng, P->nchunks, -P->dv / nk, s));
+    OCCRIK_HIP(launch_contract<T>(chi, W, P->Kpart, P->Kmi, nk, nao, nocc, ng, P->nchunks, -P->dv / nk,
+                                  P->params.precision, s));
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[3], s));
     if (dKmi) OCCRIK_HIP(hipMemcpyAsync(dKmi, P->Kmi, sizeof(double2) * nk * nao * nocc, hipMemcpyDeviceToDevice, s));
     OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, s));

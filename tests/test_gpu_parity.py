@@ -182,3 +182,17 @@ def test_fused_pass3_variants_on_a_specialised_grid(nocc, kbatch, mode):
     assert rel(out["Kmi"], ref["Kmi"]) < TOL64
     assert rel(out["K"], ref["K"]) < TOL64
     assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+
+
+@pytest.mark.parametrize("n", [24, 30, 32, 36, 40, 48])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_every_specialised_grid_size_fp64(n, mode):
+    """Each compile-time grid specialisation against the oracle (small k-mesh and basis)."""
+    prob = W.small_problem(kmesh=(1, 2, 1), grid=(n, n, n), nocc=3, counts=(2, 1, 1), seed=40 + n)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, mode)
+    plan, out = run_gpu(prob, C, mode)
+    ph = periodic_phase(prob)
+    assert rel(plan.intermediate("W").cpu().numpy(), ref["W"] * ph[:, None, :]) < TOL64
+    assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+    assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
