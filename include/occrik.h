@@ -97,6 +97,14 @@ enum {
                                      and FP32 accumulation */
 };
 
+/* Plan flags (occrik_params.flags, bitwise or). */
+enum {
+    OCCRIK_FLAG_LDS_FFT = 1       /* run every pair-pass transform as an LDS Stockham FFT; by
+                                     default cubic grids with N in {24, 32, 36, 40, 48} hold each
+                                     line in the registers of a lane pair instead.  Same results
+                                     up to rounding; meant for cross-checks and timing. */
+};
+
 typedef struct {
     double lattice[9];            /* rows a_1, a_2, a_3 in bohr, row-major */
     int32_t natm;
@@ -120,7 +128,7 @@ typedef struct {
     int32_t precision;            /* OCCRIK_PREC_* */
     double lattice_tol;           /* lattice-sum truncation, e.g. 1e-12; must be in (0, 1e-3] */
     int32_t kbatch;               /* summed k-points per FFT batch; 0 = chosen by the plan */
-    int32_t flags;                /* reserved, must be 0 */
+    int32_t flags;                /* OCCRIK_FLAG_* bits; other bits must be 0 */
     size_t mem_budget;            /* device bytes the plan may allocate; 0 = no limit */
 } occrik_params;
 

@@ -21,6 +21,7 @@ STATUS_NAMES = {
 KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR = 0, 1, 2
 NYQUIST_FFTFREQ, NYQUIST_SYMMETRIC = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_SPLIT = 0, 1, 2
+FLAG_LDS_FFT = 1
 
 # every function the header declares, with (restype, argtypes)
 c_int32 = ctypes.c_int32

@@ -35,6 +35,7 @@ struct PairBatch {
     double recip[9];          // reciprocal vectors b_1, b_2, b_3 (rows)
     int splits;               // pass-3 splits of the (b, i) sum of the a-side
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
+    int regfft;               // 1: register-resident line FFTs (cubic grids of reg_fft_size)
 };
 
 // pass-2 workgroups per m2-slab of a batch
@@ -51,6 +52,18 @@ hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, doubl
 template <typename T>
 hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
                         const cplx<T>* tw, hipStream_t s);
+// register-FFT variants of the three passes (pairs_reg.hip)
+bool reg_fft_size(int n1, int n2, int n3);
+template <typename T>
+bool reg_pass3_ok(const PairBatch& B);
+template <typename T>
+hipError_t launch_pass1_reg(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, hipStream_t s);
+template <typename T>
+hipError_t launch_pass2_reg(const PairBatch& B, cplx<T>* X, double* parts, int deriv_only, hipStream_t s);
+template <typename T>
+hipError_t launch_pass3_reg(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
+                            hipStream_t s);
+
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);
 

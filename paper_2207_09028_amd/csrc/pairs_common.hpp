@@ -1,0 +1,103 @@
+// Device helpers shared by the pair-pass kernels (LDS Stockham and register forms).
+#pragma once
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace occrik {
+namespace pairs {
+
+template <typename T>
+__device__ inline void load_twiddles(cplx<T>* dst, const cplx<T>* src) {
+    for (int t = threadIdx.x; t < 3 * kMaxN; t += blockDim.x) dst[t] = src[t];
+}
+
+__device__ inline int freq(int t, int n) { return (t < (n + 1) / 2) ? t : t - n; }
+
+__device__ inline void kfrac_of(int idx, int M1, int M2, int M3, double* f) {
+    const int k3 = idx % M3;
+    const int k2 = (idx / M3) % M2;
+    const int k1 = idx / (M2 * M3);
+    f[0] = double(k1) / M1;
+    f[1] = double(k2) / M2;
+    f[2] = double(k3) / M3;
+}
+
+// f(x) at x^2 = x2 (paper eq. recipcoul) with this build's x = 0 rule.
+template <typename T>
+__device__ inline T kernel_f(T x2, int kind, T omega) {
+    if (kind == OCCRIK_KERNEL_COULOMB) {
+        return x2 == T(0) ? T(0) : T(12.566370614359172953850573533118) / x2;
+    } else if (kind == OCCRIK_KERNEL_ERF_LR) {
+        return x2 == T(0) ? T(0) : T(12.566370614359172953850573533118) / x2 * exp(-x2 / (T(4) * omega * omega));
+    } else {
+        return x2 == T(0) ? T(3.1415926535897932384626433832795) / (omega * omega)
+                          : T(12.566370614359172953850573533118) / x2 * (-expm1(-x2 / (T(4) * omega * omega)));
+    }
+}
+
+template <typename T>
+__device__ inline T kernel_dfdw(T x2, int kind, T omega) {
+    const T w3 = omega * omega * omega;
+    if (kind == OCCRIK_KERNEL_ERF_LR) {
+        return x2 == T(0) ? T(0) : T(6.283185307179586476925286766559) / w3 * exp(-x2 / (T(4) * omega * omega));
+    } else if (kind == OCCRIK_KERNEL_ERFC_SR) {
+        return x2 == T(0) ? -T(6.283185307179586476925286766559) / w3
+                          : -T(6.283185307179586476925286766559) / w3 * exp(-x2 / (T(4) * omega * omega));
+    }
+    return T(0);
+}
+
+template <typename T>
+struct Recip {
+    T b[9];
+};
+
+template <typename T>
+__device__ inline T momentum_sq(const Recip<T>& rc, double q0, double q1, double q2, int m1, int m2, int m3) {
+    const T a = T(m1 + q0), b = T(m2 + q1), c = T(m3 + q2);
+    const T gx = a * rc.b[0] + b * rc.b[3] + c * rc.b[6];
+    const T gy = a * rc.b[1] + b * rc.b[4] + c * rc.b[7];
+    const T gz = a * rc.b[2] + b * rc.b[5] + c * rc.b[8];
+    return gx * gx + gy * gy + gz * gz;
+}
+
+// Sizes: compile-time when NN > 0 (cubic NN^3 grid), else taken from the batch.
+template <int NN>
+struct Dims {
+    int n1, n2, n3;
+    __device__ explicit Dims(const PairBatch& B)
+        : n1(NN ? NN : B.N1), n2(NN ? NN : B.N2), n3(NN ? NN : B.N3) {}
+};
+
+template <typename T, int NN, int DIR>
+__device__ __forceinline__ void lines(int n, cplx<T>* buf, int count, int es, int ls, const cplx<T>* tw) {
+    if constexpr (NN > 0) fft_lines<T, NN, DIR, NN>(buf, count, es, ls, tw);
+    else fft_lines_n<T, DIR>(n, buf, count, es, ls, tw);
+}
+
+// index of the stored pair (i, j), i <= j, of a diagonal block: rows of the upper triangle
+__device__ inline int tri_index(int i, int j, int nocc) { return i * nocc - (i * (i - 1)) / 2 + (j - i); }
+
+// Stored pair slot -> (b, i, j).
+__device__ inline void decode_slot(const PairBatch& B, int slot, int& b, int& i, int& j) {
+    const int nn = B.nocc * B.nocc;
+    if (B.diag && slot < B.ntri) {
+        int r = 0;
+        while (r + 1 < B.nocc && tri_index(r + 1, r + 1, B.nocc) <= slot) ++r;
+        b = B.a;
+        i = r;
+        j = r + (slot - tri_index(r, r, B.nocc));
+        return;
+    }
+    const int s = slot - (B.diag ? B.ntri : 0);
+    const int blk = s / nn;
+    const int rem = s - blk * nn;
+    b = B.b0 + (B.diag ? 1 : 0) + blk;
+    i = rem / B.nocc;
+    j = rem - i * B.nocc;
+}
+
+
+}  // namespace pairs
+}  // namespace occrik

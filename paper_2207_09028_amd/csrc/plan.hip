@@ -368,6 +368,7 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     std::memcpy(B.recip, P->recip, sizeof(B.recip));
     B.splits = splits_for(P, nb);
     B.parseval = 0;
+    B.regfft = (!(P->params.flags & OCCRIK_FLAG_LDS_FFT) && reg_fft_size(B.N1, B.N2, B.N3)) ? 1 : 0;
     return B;
 }
 
@@ -494,7 +495,7 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
     if (pr->nyquist < 0 || pr->nyquist > 1) return fail(OCCRIK_ERR_INVALID_ARG, "unknown nyquist mode");
     if (pr->precision < 0 || pr->precision > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown precision");
     if (!(pr->lattice_tol > 0.0 && pr->lattice_tol <= 1e-3)) return fail(OCCRIK_ERR_INVALID_ARG, "lattice_tol");
-    if (pr->flags != 0) return fail(OCCRIK_ERR_INVALID_ARG, "flags must be 0");
+    if (pr->flags & ~OCCRIK_FLAG_LDS_FFT) return fail(OCCRIK_ERR_INVALID_ARG, "unknown bits in flags");
     if (pr->kbatch < 0) return fail(OCCRIK_ERR_INVALID_ARG, "kbatch must be >= 0");
     return OCCRIK_OK;
 }

@@ -41,6 +41,7 @@ class PlanSpec:
     lattice_tol: float = 1e-12
     kbatch: int = 0
     mem_budget: int = 0
+    flags: int = 0
 
     @classmethod
     def from_problem(cls, prob, **overrides):
@@ -77,7 +78,7 @@ class Plan:
                            self._se.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         params = _lib.Params((ctypes.c_int32 * 3)(*spec.kmesh), (ctypes.c_int32 * 3)(*spec.grid), int(spec.nocc),
                              int(spec.kernel), float(spec.omega), int(spec.nyquist), int(spec.precision),
-                             float(spec.lattice_tol), int(spec.kbatch), 0, int(spec.mem_budget))
+                             float(spec.lattice_tol), int(spec.kbatch), int(spec.flags), int(spec.mem_budget))
         handle = _lib.PlanP()
         with torch.cuda.device(self.device):
             st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params),

@@ -171,14 +171,15 @@ def test_pair_reuse_with_split_rows():
         assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
 
 
+@pytest.mark.parametrize("flags", [0, pkg.FLAG_LDS_FFT])
 @pytest.mark.parametrize("nocc,kbatch,mode", [(10, 0, "symmetric"), (3, 3, "symmetric"), (5, 2, "fftfreq"),
-                                              (8, 0, "fftfreq")])
-def test_fused_pass3_variants_on_a_specialised_grid(nocc, kbatch, mode):
-    """24^3 grid: the fused pass 3 with 8 or 16 orbital lanes, split rows and both Nyquist modes."""
+                                              (8, 0, "fftfreq"), (8, 3, "symmetric")])
+def test_fused_pass3_variants_on_a_specialised_grid(nocc, kbatch, mode, flags):
+    """24^3 grid: register and LDS transforms, 8 or 16 orbital lanes in pass 3, split rows, both Nyquist modes."""
     prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=nocc, counts=(2, 2, 1), seed=21 + nocc)
     C = W.random_coefficients(prob)
     ref = oracle_result(prob, C, mode)
-    _, out = run_gpu(prob, C, mode, kbatch=kbatch)
+    _, out = run_gpu(prob, C, mode, kbatch=kbatch, flags=flags)
     assert rel(out["Kmi"], ref["Kmi"]) < TOL64
     assert rel(out["K"], ref["K"]) < TOL64
     assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
@@ -196,3 +197,25 @@ def test_every_specialised_grid_size_fp64(n, mode):
     assert rel(plan.intermediate("W").cpu().numpy(), ref["W"] * ph[:, None, :]) < TOL64
     assert rel(out["Kmi"], ref["Kmi"]) < TOL64
     assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+
+
+@pytest.mark.parametrize("n", [24, 32, 36, 40, 48])
+@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_register_and_lds_transforms_agree(n, precision, mode):
+    """The register-resident line FFTs against the LDS Stockham passes on the same plan inputs.
+
+    Both compute the same sums in a different order, so they agree to the working
+    precision's rounding: 1e-12 relative in FP64, 2e-6 relative in FP32 (a few ulps of
+    complex64 accumulated over log N butterfly levels and 8 orbitals).
+    """
+    prob = W.small_problem(kmesh=(1, 2, 2), grid=(n, n, n), nocc=8, counts=(2, 2, 1), seed=60 + n)
+    C = W.random_coefficients(prob)
+    tol = 1e-12 if precision == pkg.PREC_FP64 else 2e-6
+    p_reg, o_reg = run_gpu(prob, C, mode, precision=precision)
+    p_lds, o_lds = run_gpu(prob, C, mode, precision=precision, flags=pkg.FLAG_LDS_FFT)
+    w_reg = p_reg.intermediate("W").cpu().numpy()
+    w_lds = p_lds.intermediate("W").cpu().numpy()
+    assert rel(w_reg, w_lds) < tol
+    assert rel(o_reg["Kmi"], o_lds["Kmi"]) < tol
+    assert abs(o_reg["Ex"][0] - o_lds["Ex"][0]) < tol * abs(o_lds["Ex"][0])
