@@ -48,6 +48,7 @@ class Geometry:
         self.kcart = self.kfrac @ self.recip
         self.nk = self.kfrac.shape[0]
         self.miller = lat_mod.miller_grid(self.grid)
+        self.rcut = kernels.truncation_radius(self.nk, self.omega_cell)
 
     def momentum_sq(self, q_frac, mirror=False):
         """|G_m + q|^2 over the DFT grid; ``mirror`` flips Nyquist components to +N/2."""
@@ -62,10 +63,15 @@ class Geometry:
 
     def kernel_on_grid(self, k2, k1, kind, omega, nyquist="fftfreq", derivative=False):
         q = self.kfrac[k2] - self.kfrac[k1]
-        fn = kernels.kernel_domega if derivative else kernels.kernel_values
-        v = fn(self.momentum_sq(q), kind, omega)
+        if derivative:
+            def fn(x2):
+                return kernels.kernel_domega(x2, kind, omega)
+        else:
+            def fn(x2):
+                return kernels.kernel_values(x2, kind, omega, self.rcut)
+        v = fn(self.momentum_sq(q))
         if nyquist == "symmetric":
-            v = 0.5 * (v + fn(self.momentum_sq(q, mirror=True), kind, omega))
+            v = 0.5 * (v + fn(self.momentum_sq(q, mirror=True)))
         elif nyquist != "fftfreq":
             raise ValueError(nyquist)
         return v.reshape(self.grid)

@@ -434,3 +434,54 @@ def test_mutation_missing_bloch_phase_fails_overlap(monkeypatch):
     monkeypatch.setattr(collocation.lat_mod, "kpoints_fractional", lambda km: 0.0 * orig(km))
     with pytest.raises(AssertionError):
         test_grid_overlap_matches_analytic_overlap()
+
+
+# ----------------------------------------------------------------------------
+# Truncated Coulomb kernel (Sec. II.A, Spencer-Alavi): 1/r cut off at R_c with
+# 4 pi R_c^3 / 3 = N_k Omega
+# ----------------------------------------------------------------------------
+
+def test_truncated_coulomb_kernel_matches_radial_quadrature():
+    """f(G) = int_{r < R_c} e^{-iG.r} / r d^3r = (4 pi / G) int_0^{R_c} sin(G r) dr, by quadrature."""
+    from scipy.integrate import quad
+    rc = 7.3
+    g = np.array([1e-7, 0.05, 0.4, 1.7, 6.1, 23.0])
+    f = kernels.kernel_values(g * g, kernels.TRUNC_COULOMB, 0.0, rc)
+    for gi, fi in zip(g, f):
+        val, _ = quad(lambda r: 4.0 * math.pi * math.sin(gi * r) / gi, 0.0, rc, limit=400)
+        assert abs(fi - val) < 1e-10 * max(abs(val), 1.0), (gi, fi, val)
+    f0 = kernels.kernel_values(np.array([0.0]), kernels.TRUNC_COULOMB, 0.0, rc)[0]
+    assert abs(f0 - 2.0 * math.pi * rc * rc) < 1e-12 * f0          # int_{r<R_c} d^3r / r
+    assert kernels.truncation_radius(8, 10.0) ** 3 * 4.0 * math.pi / 3.0 == pytest.approx(80.0, rel=1e-14)
+
+
+def _isolated_gaussian_exchange_truncated(L, n, kmesh, alpha=0.6):
+    cell = W.cubic_cell(L, [(0.5, 0.5, 0.5)])
+    basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
+    prob = W.Problem("sgauss", cell, basis, kmesh, (n, n, n), 1, seed=0, kernel=kernels.TRUNC_COULOMB)
+    C = W.random_coefficients(prob)
+    return occrik.build(prob, C, want_k=False)["Ex"]
+
+
+def test_truncated_coulomb_gives_the_isolated_gaussian_exchange_at_gamma():
+    """With the cut-off sphere inside one cell's reach no periodic image interacts, so one
+    normalised s-Gaussian has E_x = -sqrt(a/pi) exactly (no Madelung term), G = 0 included."""
+    alpha = 0.6
+    assert abs(_isolated_gaussian_exchange_truncated(24.0, 64, (1, 1, 1), alpha) + math.sqrt(alpha / math.pi)) < 1e-12
+
+
+def test_truncated_coulomb_gives_the_isolated_gaussian_exchange_on_a_kmesh():
+    """A lattice of well separated s-Gaussians (spacing 8 bohr, 3x3x3 k-points): R_c now comes
+    from the 24 bohr k-mesh supercell, and the per-cell E_x is again -sqrt(a/pi)."""
+    alpha = 0.6
+    assert abs(_isolated_gaussian_exchange_truncated(8.0, 28, (3, 3, 3), alpha) + math.sqrt(alpha / math.pi)) < 1e-12
+
+
+def test_mutation_truncation_radius_without_kpoints_fails(monkeypatch):
+    """R_c from Omega alone (N_k dropped) cuts each Gaussian's own tail: the k-mesh pin's
+    1e-12 bar catches it by orders of magnitude."""
+    real = kernels.truncation_radius
+    monkeypatch.setattr(kernels, "truncation_radius", lambda nk, vol: real(1, vol))
+    alpha = 0.6
+    err = abs(_isolated_gaussian_exchange_truncated(8.0, 28, (3, 3, 3), alpha) + math.sqrt(alpha / math.pi))
+    assert err > 1e-9

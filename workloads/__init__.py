@@ -41,6 +41,7 @@ BOHR_PER_ANGSTROM = 1.0 / 0.529177210903
 KERNEL_COULOMB = 0
 KERNEL_ERF_LR = 1
 KERNEL_ERFC_SR = 2
+KERNEL_TRUNC_COULOMB = 3
 
 
 @dataclass
