@@ -74,7 +74,12 @@ typedef enum {
 enum {
     OCCRIK_KERNEL_COULOMB = 0,    /* 4 pi / x^2;                 x = 0 term zeroed */
     OCCRIK_KERNEL_ERF_LR = 1,     /* 4 pi / x^2 exp(-x^2/4w^2);  x = 0 term zeroed */
-    OCCRIK_KERNEL_ERFC_SR = 2     /* 4 pi / x^2 (1 - exp(-x^2/4w^2)); x = 0 term pi / w^2 */
+    OCCRIK_KERNEL_ERFC_SR = 2,    /* 4 pi / x^2 (1 - exp(-x^2/4w^2)); x = 0 term pi / w^2 */
+    OCCRIK_KERNEL_TRUNC_COULOMB = 3   /* 4 pi / x^2 (1 - cos(x R_c)); x = 0 term 2 pi R_c^2.
+                                     1/r cut off at R_c (Sec. II.A, the Spencer-Alavi kernel),
+                                     with 4 pi R_c^3 / 3 = N_k Omega (the k-mesh supercell's
+                                     volume).  omega is ignored; d E_x / d omega is 0.
+                                     Evaluated in FP64 in every precision mode. */
 };
 
 /* Treatment of the even-N Nyquist planes in the kernel multiply.
@@ -97,12 +102,24 @@ enum {
                                      and FP32 accumulation */
 };
 
-/* Plan flags (occrik_params.flags, bitwise or). */
+/* Plan flags (occrik_params.flags, bitwise or).  Complex64 plans (PREC_FP32,
+ * PREC_FP32_SPLIT) on cubic grids with N in {24, 32, 36, 40, 48} run pass 2 of the
+ * pair round trip (forward transform along n1, kernel multiply, inverse along m1
+ * and m3) with each line held in the registers of a lane pair; every other pass,
+ * and every FP64 plan, uses LDS Stockham transforms.  The flags change that choice
+ * for cross-checks and timing; results agree to rounding. */
 enum {
-    OCCRIK_FLAG_LDS_FFT = 1       /* run every pair-pass transform as an LDS Stockham FFT; by
-                                     default cubic grids with N in {24, 32, 36, 40, 48} hold each
-                                     line in the registers of a lane pair instead.  Same results
-                                     up to rounding; meant for cross-checks and timing. */
+    OCCRIK_FLAG_LDS_FFT = 1,      /* every pair-pass transform as an LDS Stockham FFT */
+    OCCRIK_FLAG_REG_FFT_ALL = 2,  /* passes 1 and 3 in registers too (complex64, cubic grids
+                                     of the sizes above, pass 3 for nocc <= 8); not with LDS_FFT */
+    OCCRIK_FLAG_DIRECT = 4        /* integral-direct (Sec. II.E, Alg. 4): chi~ is never stored;
+                                     every build collocates it chunk by chunk, once for the
+                                     orbitals and once for the contraction.  The plan also
+                                     switches to it by itself when the stored chi~ would not
+                                     fit in mem_budget (or, with no budget, in the device
+                                     memory free at plan creation).  Its chunks hold chi~ of
+                                     at most 2 GiB (or mem_budget / 8) for every k and AO.
+                                     Results are bitwise those of the stored mode. */
 };
 
 typedef struct {
@@ -139,10 +156,12 @@ typedef struct {
     int32_t grid[3], kmesh[3];
     int32_t precision, nyquist, kernel, kbatch;
     double omega, cell_volume;
-    size_t bytes_chi;             /* Bloch AOs on the grid */
+    size_t bytes_chi;             /* Bloch AOs on the grid (0 for integral-direct plans) */
     size_t bytes_workspace;       /* everything else the plan allocated */
     int64_t pair_transforms;      /* forward+inverse 3D FFT pairs per build */
     double plan_seconds;          /* wall time of occrik_plan_create */
+    int32_t integral_direct;      /* 1: chi~ collocated per build (OCCRIK_FLAG_DIRECT) */
+    int32_t colloc_chunk;         /* grid points per collocation chunk */
 } occrik_plan_info;
 
 /* Per-phase device timings of the last build(s), from HIP events recorded on
@@ -164,7 +183,7 @@ typedef struct {
 /* Create a plan: validates the inputs, derives the reciprocal lattice and the
  * per-shell image lists, allocates the device workspaces and collocates the
  * Bloch AOs on the grid (stored for every build, as the paper assumes in
- * Sec. II.A).  device: HIP ordinal; stream: a hipStream_t or NULL for the
+ * Sec. II.A; integral-direct plans, see OCCRIK_FLAG_DIRECT, collocate per build).  device: HIP ordinal; stream: a hipStream_t or NULL for the
  * default stream.  *out is NULL on failure. */
 occrik_status occrik_plan_create(const occrik_cell *cell, const occrik_basis *basis,
                                  const occrik_params *params, int device, void *stream,

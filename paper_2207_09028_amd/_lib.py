@@ -18,10 +18,12 @@ STATUS_NAMES = {
     4: "OCCRIK_ERR_NOT_PD", 5: "OCCRIK_ERR_NONFINITE", 6: "OCCRIK_ERR_DEVICE", 7: "OCCRIK_ERR_STATE",
 }
 
-KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR = 0, 1, 2
+KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR, KERNEL_TRUNC_COULOMB = 0, 1, 2, 3
 NYQUIST_FFTFREQ, NYQUIST_SYMMETRIC = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_SPLIT = 0, 1, 2
 FLAG_LDS_FFT = 1
+FLAG_REG_FFT_ALL = 2
+FLAG_DIRECT = 4
 
 # every function the header declares, with (restype, argtypes)
 c_int32 = ctypes.c_int32
@@ -51,7 +53,8 @@ class PlanInfo(ctypes.Structure):
                 ("precision", c_int32), ("nyquist", c_int32), ("kernel", c_int32), ("kbatch", c_int32),
                 ("omega", c_double), ("cell_volume", c_double),
                 ("bytes_chi", c_size_t), ("bytes_workspace", c_size_t),
-                ("pair_transforms", ctypes.c_int64), ("plan_seconds", c_double)]
+                ("pair_transforms", ctypes.c_int64), ("plan_seconds", c_double),
+                ("integral_direct", c_int32), ("colloc_chunk", c_int32)]
 
 
 class Profile(ctypes.Structure):

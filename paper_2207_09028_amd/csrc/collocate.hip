@@ -36,8 +36,9 @@ template <int L>
 __global__ void __launch_bounds__(256) fold_kernel(double* __restrict__ phi, const double4* __restrict__ img,
                                                    const int* __restrict__ bucket, ShellDev sh, CollocGeom g) {
     constexpr int NC = (L + 1) * (L + 2) / 2;
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= g.ng) return;
+    const int nl = blockIdx.x * 256 + threadIdx.x;
+    if (nl >= g.cnt) return;
+    const int n = g.n0 + nl;
     const int n3 = n % g.N[2];
     const int n2 = (n / g.N[2]) % g.N[1];
     const int n1 = n / (g.N[1] * g.N[2]);
@@ -60,14 +61,23 @@ __global__ void __launch_bounds__(256) fold_kernel(double* __restrict__ phi, con
             for (int c = 0; c < NC; ++c) acc[c] += m[c] * e;
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) phi[((size_t)c * g.nk + cell) * g.ng + n] = sh.norm[c] * acc[c];
+        for (int c = 0; c < NC; ++c) phi[((size_t)c * g.nk + cell) * g.cnt + nl] = sh.norm[c] * acc[c];
     }
 }
 
 // DFT along one k-mesh axis of a [M1][M2][M3][ng] array with e^{+2 pi i kappa l / M}.
 // real_in: the input is real (first axis), else complex.
-__global__ void axis_dft_kernel(const double* __restrict__ in_real, const double2* __restrict__ in_c,
-                                double2* __restrict__ out, int M, int inner, int outer, int ng, int real_in) {
+__global__ void __launch_bounds__(256) axis_dft_kernel(const double* __restrict__ in_real,
+                                                       const double2* __restrict__ in_c, double2* __restrict__ out,
+                                                       int M, int inner, int outer, int ng, int real_in) {
+    // e^{2 pi i t / M}, t = kappa l mod M, once per workgroup
+    __shared__ double2 tw[16];
+    if (threadIdx.x < M) {
+        double sn, cs;
+        sincospi(2.0 * double(threadIdx.x) / double(M), &sn, &cs);
+        tw[threadIdx.x] = make_double2(cs, sn);
+    }
+    __syncthreads();
     // thread over (outer index o, inner index q, grid point n); the axis has stride inner*ng
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t per = (size_t)inner * ng;
@@ -84,11 +94,9 @@ __global__ void axis_dft_kernel(const double* __restrict__ in_real, const double
     for (int kap = 0; kap < M; ++kap) {
         double sx = 0.0, sy = 0.0;
         for (int l = 0; l < M; ++l) {
-            const int t = (kap * l) % M;
-            double sn, cs;
-            sincospi(2.0 * double(t) / double(M), &sn, &cs);
-            sx += cs * v[l].x - sn * v[l].y;
-            sy += cs * v[l].y + sn * v[l].x;
+            const double2 w = tw[(kap * l) % M];
+            sx += w.x * v[l].x - w.y * v[l].y;
+            sy += w.x * v[l].y + w.y * v[l].x;
         }
         out[base + kap * stride] = make_double2(sx, sy);
     }
@@ -96,11 +104,12 @@ __global__ void axis_dft_kernel(const double* __restrict__ in_real, const double
 
 template <typename T>
 __global__ void store_kernel(const double2* __restrict__ chik, cplx<T>* __restrict__ chi, int mu, int nao,
-                             CollocGeom g) {
+                             size_t ldc, size_t coff, CollocGeom g) {
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)g.nk * g.ng) return;
-    const int k = (int)(gid / g.ng);
-    const int n = (int)(gid - (size_t)k * g.ng);
+    if (gid >= (size_t)g.nk * g.cnt) return;
+    const int k = (int)(gid / g.cnt);
+    const int nl = (int)(gid - (size_t)k * g.cnt);
+    const int n = g.n0 + nl;
     const int k3 = k % g.M[2], k2 = (k / g.M[2]) % g.M[1], k1 = k / (g.M[1] * g.M[2]);
     const int n3 = n % g.N[2], n2 = (n / g.N[2]) % g.N[1], n1 = n / (g.N[1] * g.N[2]);
     // k.r_n = 2 pi sum_d kappa_d n_d / (M_d N_d), reduced exactly before the FP64 division
@@ -110,14 +119,14 @@ __global__ void store_kernel(const double2* __restrict__ chik, cplx<T>* __restri
     double sn, cs;
     sincospi(-2.0 * fr, &sn, &cs);
     const double2 v = chik[gid];
-    chi[((size_t)k * nao + mu) * g.ng + n] = mk<T>(T(cs * v.x - sn * v.y), T(cs * v.y + sn * v.x));
+    chi[((size_t)k * nao + mu) * ldc + coff + nl] = mk<T>(T(cs * v.x - sn * v.y), T(cs * v.y + sn * v.x));
 }
 
 }  // namespace
 
 hipError_t launch_colloc_fold(double* phi, const double4* img, const int* bucket, const ShellDev& sh,
                               const CollocGeom& g, hipStream_t s) {
-    dim3 grid((unsigned)((g.ng + 255) / 256));
+    dim3 grid((unsigned)((g.cnt + 255) / 256));
     switch (sh.l) {
         case 0: hipLaunchKernelGGL(fold_kernel<0>, grid, dim3(256), 0, s, phi, img, bucket, sh, g); break;
         case 1: hipLaunchKernelGGL(fold_kernel<1>, grid, dim3(256), 0, s, phi, img, bucket, sh, g); break;
@@ -130,36 +139,39 @@ hipError_t launch_colloc_fold(double* phi, const double4* img, const int* bucket
 
 hipError_t launch_colloc_kdft(const double* phi_real, double2* work0, double2* work1, const CollocGeom& g,
                               hipStream_t s, double2** result) {
-    // axes in the order 3, 2, 1; array layout [M1][M2][M3][ng]
+    // axes in the order 3, 2, 1; array layout [M1][M2][M3][cnt]
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
-    const size_t total = (size_t)g.nk * g.ng;
+    const size_t total = (size_t)g.nk * g.cnt;
     const unsigned blocks = (unsigned)((total + 255) / 256);
     // axis 3: inner = 1, outer = M1*M2
     hipLaunchKernelGGL(axis_dft_kernel, dim3(blocks), dim3(256), 0, s, phi_real, (const double2*)nullptr, work0, M3, 1,
-                       M1 * M2, g.ng, 1);
+                       M1 * M2, g.cnt, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // axis 2: inner = M3, outer = M1
     hipLaunchKernelGGL(axis_dft_kernel, dim3(blocks), dim3(256), 0, s, (const double*)nullptr, work0, work1, M2, M3,
-                       M1, g.ng, 0);
+                       M1, g.cnt, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // axis 1: inner = M2*M3, outer = 1
     hipLaunchKernelGGL(axis_dft_kernel, dim3(blocks), dim3(256), 0, s, (const double*)nullptr, work1, work0, M1,
-                       M2 * M3, 1, g.ng, 0);
+                       M2 * M3, 1, g.cnt, 0);
     *result = work0;
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_colloc_store(const double2* chik, cplx<T>* chi, int mu, int nao, const CollocGeom& g, hipStream_t s) {
-    const size_t total = (size_t)g.nk * g.ng;
-    hipLaunchKernelGGL(store_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, chik, chi, mu, nao, g);
+hipError_t launch_colloc_store(const double2* chik, cplx<T>* dst, int mu, int nao, size_t ldc, size_t coff,
+                               const CollocGeom& g, hipStream_t s) {
+    const size_t total = (size_t)g.nk * g.cnt;
+    hipLaunchKernelGGL(store_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, chik, dst, mu, nao, ldc,
+                       coff, g);
     return hipGetLastError();
 }
 
-template hipError_t launch_colloc_store<float>(const double2*, cplx<float>*, int, int, const CollocGeom&, hipStream_t);
-template hipError_t launch_colloc_store<double>(const double2*, cplx<double>*, int, int, const CollocGeom&,
-                                                hipStream_t);
+template hipError_t launch_colloc_store<float>(const double2*, cplx<float>*, int, int, size_t, size_t,
+                                               const CollocGeom&, hipStream_t);
+template hipError_t launch_colloc_store<double>(const double2*, cplx<double>*, int, int, size_t, size_t,
+                                                const CollocGeom&, hipStream_t);
 
 }  // namespace occrik

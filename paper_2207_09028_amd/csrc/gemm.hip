@@ -94,16 +94,17 @@ constexpr int kFlush = 32;        // FP32 MFMA steps (x4 forms) between FP64 flu
 // orbitals: one workgroup = 4 waves x 4 tiles x 16 points of one k
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__ chi, const double2* __restrict__ C,
-                                                     cplx<T>* __restrict__ psi, int nao, int nocc, int ng) {
+__global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__ chi, size_t ldc,
+                                                     const double2* __restrict__ C, cplx<T>* __restrict__ psi,
+                                                     int nao, int nocc, int ng, int n0, int cnt) {
     typedef typename Acc<MODE>::type acc_t;
     constexpr int KCH = 2 * kOrbChunk;                  // real k values per chunk
     __shared__ T alds[kMaxRowTiles][16][KCH];
     const int k = blockIdx.y;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int nbase = (blockIdx.x * 4 + wave) * kOrbTiles * 16;
+    const int nbase = (blockIdx.x * 4 + wave) * kOrbTiles * 16;    // point of the chunk
     const int rt_n = (2 * nocc + 15) / 16;
-    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * k * nao * ng;
+    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * k * nao * ldc;
     const double2* Ck = C + (size_t)k * nao * nocc;
     acc_t acc[kMaxRowTiles][kOrbTiles];
 #pragma unroll
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll
                 for (int t = 0; t < kOrbTiles; ++t) {
                     const int n = nbase + 16 * t + (l & 15);
-                    bv[t] = (mu < nao && n < ng) ? chir[2 * ((size_t)mu * ng + n) + cc] : T(0);
+                    bv[t] = (mu < nao && n < cnt) ? chir[2 * ((size_t)mu * ldc + n) + cc] : T(0);
                 }
 #pragma unroll
                 for (int rt = 0; rt < kMaxRowTiles; ++rt) {
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll
                     for (int v = 0; v < 8; ++v) {
                         const int kk = kk0 + v, mu = m0 + (kk >> 1), cc = kk & 1;
-                        bv[t][v] = (mu < nao && n < ng) ? (float)chir[2 * ((size_t)mu * ng + n) + cc] : 0.f;
+                        bv[t][v] = (mu < nao && n < cnt) ? (float)chir[2 * ((size_t)mu * ldc + n) + cc] : 0.f;
                     }
                 }
 #pragma unroll
@@ -180,7 +181,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rt * 16 + out_row<MODE>(l, r), j = row >> 1, c = row & 1;
-                if (j < nocc && n < ng) psir[2 * ((size_t)j * ng + n) + c] = T(acc[rt][t][r]);
+                if (j < nocc && n < cnt) psir[2 * ((size_t)j * ng + n0 + n) + c] = T(acc[rt][t][r]);
             }
         }
     }
@@ -190,18 +191,20 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 // contraction: one wave = 16 AOs x (2 nocc) columns over one chunk of the grid
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__ chi, const cplx<T>* __restrict__ W,
-                                                     double* __restrict__ Kpart, int nao, int nocc, int ng,
-                                                     int chunk) {
+__global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__ chi, size_t ldc, int chi_n0,
+                                                     const cplx<T>* __restrict__ W, double* __restrict__ Kpart,
+                                                     int nao, int nocc, int ng, int chunk, int c_first, int nchunks) {
     typedef typename Acc<MODE>::type acc_t;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int c = blockIdx.x, nchunks = gridDim.x;
+    const int c = c_first + blockIdx.x;
     const int mu0 = (blockIdx.y * 4 + wave) * 16;
     const int k = blockIdx.z;
     const int n0 = c * chunk, n1 = min(ng, n0 + chunk);
     const int ct_n = (2 * nocc + 15) / 16;
     const int mu = mu0 + (l & 15);
-    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * ((size_t)k * nao + min(mu, nao - 1)) * ng;
+    // chi holds grid points chi_n0.. of each (k, mu) row
+    const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * ((size_t)k * nao + min(mu, nao - 1)) * ldc -
+                    (ptrdiff_t)2 * chi_n0;
     const cplx<T>* Wk = W + (size_t)k * nocc * ng;
     acc_t acc[kMaxRowTiles];
     double tot[kMaxRowTiles][4];
@@ -313,47 +316,62 @@ __global__ void contract_reduce_kernel(const double2* __restrict__ Kpart, double
 }  // namespace
 
 template <typename T>
-hipError_t launch_orbitals(const cplx<T>* chi, const double2* C, cplx<T>* psi, int nk, int nao, int nocc, int ng,
-                           int mode, hipStream_t s) {
+hipError_t launch_orbitals(const cplx<T>* chi, size_t ldc, const double2* C, cplx<T>* psi, int nk, int nao, int nocc,
+                           int ng, int n0, int cnt, int mode, hipStream_t s) {
+    if (cnt <= 0) return hipSuccess;
     const int per_wg = 4 * kOrbTiles * 16;
-    dim3 grid((unsigned)((ng + per_wg - 1) / per_wg), (unsigned)nk);
+    dim3 grid((unsigned)((cnt + per_wg - 1) / per_wg), (unsigned)nk);
     if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((orbitals_mfma<T, 0>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+        hipLaunchKernelGGL((orbitals_mfma<T, 0>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
     } else {
-        if (mode == 2) hipLaunchKernelGGL((orbitals_mfma<T, 2>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
-        else hipLaunchKernelGGL((orbitals_mfma<T, 1>), grid, dim3(256), 0, s, chi, C, psi, nao, nocc, ng);
+        if (mode == 2)
+            hipLaunchKernelGGL((orbitals_mfma<T, 2>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
+        else
+            hipLaunchKernelGGL((orbitals_mfma<T, 1>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
     }
     return hipGetLastError();
 }
 
+int contract_chunk(int ng, int nchunks) {
+    const int chunk = (ng + nchunks - 1) / nchunks;
+    return (chunk + 15) / 16 * 16;
+}
+
 template <typename T>
-hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart, double2* Kmi, int nk, int nao,
-                           int nocc, int ng, int nchunks, double scale, int mode, hipStream_t s) {
-    int chunk = (ng + nchunks - 1) / nchunks;
-    chunk = (chunk + 15) / 16 * 16;
-    dim3 grid((unsigned)nchunks, (unsigned)((nao + 63) / 64), (unsigned)nk);
+hipError_t launch_contract_part(const cplx<T>* chi, size_t ldc, int chi_n0, const cplx<T>* W, double2* Kpart, int nk,
+                                int nao, int nocc, int ng, int nchunks, int c0, int nc, int mode, hipStream_t s) {
+    if (nc <= 0) return hipSuccess;
+    const int chunk = contract_chunk(ng, nchunks);
+    dim3 grid((unsigned)nc, (unsigned)((nao + 63) / 64), (unsigned)nk);
     double* kp = reinterpret_cast<double*>(Kpart);
     if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((contract_mfma<T, 0>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
+        hipLaunchKernelGGL((contract_mfma<T, 0>), grid, dim3(256), 0, s, chi, ldc, chi_n0, W, kp, nao, nocc, ng, chunk,
+                           c0, nchunks);
     } else {
-        if (mode == 2) hipLaunchKernelGGL((contract_mfma<T, 2>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
-        else hipLaunchKernelGGL((contract_mfma<T, 1>), grid, dim3(256), 0, s, chi, W, kp, nao, nocc, ng, chunk);
+        if (mode == 2)
+            hipLaunchKernelGGL((contract_mfma<T, 2>), grid, dim3(256), 0, s, chi, ldc, chi_n0, W, kp, nao, nocc, ng,
+                               chunk, c0, nchunks);
+        else
+            hipLaunchKernelGGL((contract_mfma<T, 1>), grid, dim3(256), 0, s, chi, ldc, chi_n0, W, kp, nao, nocc, ng,
+                               chunk, c0, nchunks);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t n = (size_t)nk * nao * nocc;
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_reduce(const double2* Kpart, double2* Kmi, size_t n, int nchunks, double scale,
+                                  hipStream_t s) {
     hipLaunchKernelGGL(contract_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Kpart, Kmi, n,
                        nchunks, scale);
     return hipGetLastError();
 }
 
-template hipError_t launch_orbitals<float>(const cplx<float>*, const double2*, cplx<float>*, int, int, int, int, int,
-                                           hipStream_t);
-template hipError_t launch_orbitals<double>(const cplx<double>*, const double2*, cplx<double>*, int, int, int, int,
-                                            int, hipStream_t);
-template hipError_t launch_contract<float>(const cplx<float>*, const cplx<float>*, double2*, double2*, int, int, int,
-                                           int, int, double, int, hipStream_t);
-template hipError_t launch_contract<double>(const cplx<double>*, const cplx<double>*, double2*, double2*, int, int,
-                                            int, int, int, double, int, hipStream_t);
+template hipError_t launch_orbitals<float>(const cplx<float>*, size_t, const double2*, cplx<float>*, int, int, int,
+                                           int, int, int, int, hipStream_t);
+template hipError_t launch_orbitals<double>(const cplx<double>*, size_t, const double2*, cplx<double>*, int, int, int,
+                                            int, int, int, int, hipStream_t);
+template hipError_t launch_contract_part<float>(const cplx<float>*, size_t, int, const cplx<float>*, double2*, int, int,
+                                                int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_contract_part<double>(const cplx<double>*, size_t, int, const cplx<double>*, double2*, int,
+                                                 int, int, int, int, int, int, int, hipStream_t);
 
 }  // namespace occrik

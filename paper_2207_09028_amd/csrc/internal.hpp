@@ -31,11 +31,13 @@ struct PairBatch {
     int group;                // stored pairs per pass-2 workgroup
     int kernel, nyquist;
     double omega;
+    double rcut;              // truncated Coulomb radius R_c (4 pi R_c^3 / 3 = N_k Omega)
     double inv_ng;
     double recip[9];          // reciprocal vectors b_1, b_2, b_3 (rows)
     int splits;               // pass-3 splits of the (b, i) sum of the a-side
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
-    int regfft;               // 1: register-resident line FFTs (cubic grids of reg_fft_size)
+    int regfft;               // REGFFT_PASS* bits: passes run with register-resident line FFTs
+    float* kvals;             // regfft: [nb][m2][m1][m3] kernel values of the batch (plan workspace)
 };
 
 // pass-2 workgroups per m2-slab of a batch
@@ -52,17 +54,17 @@ hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, doubl
 template <typename T>
 hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
                         const cplx<T>* tw, hipStream_t s);
-// register-FFT variants of the three passes (pairs_reg.hip)
+// register-FFT variants of the three passes (pairs_reg.hip), complex64 only;
+// pass 3 takes at most 8 occupied orbitals.  The plan turns on the passes where
+// the register form measured faster than the LDS Stockham form (pass 2: the
+// forward, kernel multiply and two inverse transforms of a slab; passes 1 and 3
+// keep the LDS form, whose radix-8/6 stages issue fewer VALU instructions).
+enum { REGFFT_PASS1 = 1, REGFFT_PASS2 = 2, REGFFT_PASS3 = 4, REGFFT_DEFAULT = REGFFT_PASS2 };
 bool reg_fft_size(int n1, int n2, int n3);
-template <typename T>
-bool reg_pass3_ok(const PairBatch& B);
-template <typename T>
-hipError_t launch_pass1_reg(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, hipStream_t s);
-template <typename T>
-hipError_t launch_pass2_reg(const PairBatch& B, cplx<T>* X, double* parts, int deriv_only, hipStream_t s);
-template <typename T>
-hipError_t launch_pass3_reg(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
-                            hipStream_t s);
+hipError_t launch_pass1_reg(const PairBatch& B, const cplx<float>* psi, cplx<float>* X, hipStream_t s);
+hipError_t launch_pass2_reg(const PairBatch& B, cplx<float>* X, double* parts, int deriv_only, hipStream_t s);
+hipError_t launch_pass3_reg(const PairBatch& B, const cplx<float>* X, const cplx<float>* psi, cplx<float>* Wpart,
+                            cplx<float>* W, hipStream_t s);
 
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);
@@ -72,14 +74,22 @@ hipError_t launch_fill_zero(cplx<T>* p, size_t n, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s);
 
 // Grid contractions on the matrix cores; mode = OCCRIK_PREC_* (FP32_SPLIT uses split-bf16).
+// psi[k][j][n0 + t] = sum_mu C[k][mu][j] chi[k][mu][t] for t < cnt; chi rows have stride ldc
 template <typename T>
-hipError_t launch_orbitals(const cplx<T>* chi, const double2* C, cplx<T>* psi, int nk, int nao, int nocc, int ng,
-                           int mode, hipStream_t s);
+hipError_t launch_orbitals(const cplx<T>* chi, size_t ldc, const double2* C, cplx<T>* psi, int nk, int nao, int nocc,
+                           int ng, int n0, int cnt, int mode, hipStream_t s);
+// grid points per partial sum of the contraction
+int contract_chunk(int ng, int nchunks);
+// FP64 partial sums Kpart[k][mu][j][c] for chunks c in [c0, c0 + nc) of the grid
+// (nchunks chunks of contract_chunk points); chi holds the points from chi_n0 on,
+// rows of stride ldc
 template <typename T>
-hipError_t launch_contract(const cplx<T>* chi, const cplx<T>* W, double2* Kpart, double2* Kmi, int nk, int nao,
-                           int nocc, int ng, int nchunks, double scale, int mode, hipStream_t s);
+hipError_t launch_contract_part(const cplx<T>* chi, size_t ldc, int chi_n0, const cplx<T>* W, double2* Kpart, int nk,
+                                int nao, int nocc, int ng, int nchunks, int c0, int nc, int mode, hipStream_t s);
+// Kmi = scale * sum_c Kpart[..][c], c in chunk order
+hipError_t launch_contract_reduce(const double2* Kpart, double2* Kmi, size_t n, int nchunks, double scale,
+                                  hipStream_t s);
 
-// Assembly (FP64).
 hipError_t launch_check_finite(const double2* C, size_t n, int* flags, hipStream_t s);
 hipError_t launch_reset_flags_n(int* flags, int n, hipStream_t s);
 hipError_t launch_kij(const double2* C, const double2* Kmi, double2* Kij, double2* L, double* eterm, int* flags,
@@ -91,12 +101,14 @@ hipError_t launch_energy(const double* eterm, int nk, double* out, hipStream_t s
 hipError_t launch_sum_f64(const double* parts, size_t n, double scale, double* out, hipStream_t s);
 hipError_t launch_scale_copy(const double2* src, double2* dst, size_t n, double scale, hipStream_t s);
 
-// Collocation (plan time).
+// Collocation: at plan time into the stored chi~, or per build and per grid chunk in
+// integral-direct plans; both run the same per-point arithmetic.
 struct CollocGeom {
     double lat[9];            // rows a_1, a_2, a_3
     int N[3];                 // grid
     int M[3];                 // k-mesh
     int nk, ng;
+    int n0, cnt;              // the grid points [n0, n0 + cnt) collocated by one call
 };
 struct ShellDev {
     double R[3];
@@ -112,8 +124,10 @@ hipError_t launch_colloc_fold(double* phi, const double4* img, const int* bucket
 // ping-pong buffers and returns the one holding the result.
 hipError_t launch_colloc_kdft(const double* phi_real, double2* work0, double2* work1, const CollocGeom& g,
                               hipStream_t s, double2** result);
+// chi~ of component mu for the points of g: dst[(k nao + mu) ldc + coff + (n - g.n0)]
 template <typename T>
-hipError_t launch_colloc_store(const double2* chik, cplx<T>* chi, int mu, int nao, const CollocGeom& g, hipStream_t s);
+hipError_t launch_colloc_store(const double2* chik, cplx<T>* dst, int mu, int nao, size_t ldc, size_t coff,
+                               const CollocGeom& g, hipStream_t s);
 
 template <typename T>
 hipError_t launch_convert_to_c128(const cplx<T>* src, double2* dst, size_t n, hipStream_t s);

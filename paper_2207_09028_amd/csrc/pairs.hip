@@ -24,6 +24,7 @@
 // its potential is the conjugate potential.  A batch then covers the blocks
 // (a, b) with b >= a; the diagonal block stores the pairs i <= j only.
 #include <algorithm>
+#include <type_traits>
 
 #include "fft.hpp"
 #include "internal.hpp"
@@ -134,15 +135,13 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
         if (e < tile_sz) {
             const int t1 = e / N3, t3 = e - t1 * N3;
             const int m1 = freq(t1, N1), m3 = freq(t3, N3);
-            const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
             const bool nyq = sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3));
-            T f = deriv_only ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
+            T f = kernel_at<T>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
             if (nyq) {
                 const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
                 const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
                 const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
-                const T x2m = momentum_sq<T>(rc, q0, q1, q2, mm1, mm2, mm3);
-                f = T(0.5) * (f + (deriv_only ? kernel_dfdw<T>(x2m, B.kernel, om) : kernel_f<T>(x2m, B.kernel, om)));
+                f = T(0.5) * (f + kernel_at<T>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
             }
             v[t] = f;
         }
@@ -376,33 +375,80 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     const bool active = lane < LN && jl < nocc;
     load_twiddles<T>(tw, twg);
     const size_t plane_off = (size_t)n1 * PLANE + c0 + w;
-    cplx<T> acc[PT];
+    // stored slot of (b, i; jl, a) for summed pair q = (b - b0) nocc + i, and whether it
+    // holds the conjugate (lower triangle of the diagonal block)
+    auto slot_of = [&](int q, bool& cj) {
+        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        cj = false;
+        if (B.diag && bb == B.a) {
+            cj = jl < i;
+            return cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
+        }
+        return full_base + (bb - first_full) * nn + i * nocc + jl;
+    };
+    auto load_column = [&](int q, cplx<T>* dst) {
+        bool cj;
+        const cplx<T>* src = X + (size_t)(active ? slot_of(q, cj) : 0) * B.ng + plane_off;
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int m2 = r0 + t * RPI;
+            dst[t] = (active && m2 < NN) ? src[(size_t)m2 * NN] : mk<T>(T(0), T(0));
+        }
+    };
+    // Register prefetch (8 orbital lanes; 16 lanes double the per-thread rows and would
+    // spill): the next pair's column is loaded while this pair is transformed, and the
+    // a-side orbital at this thread's points, the same for every summed pair, is held.
+    constexpr bool PF = JC <= 8;
+    const cplx<T>* pa_src = psi + ((size_t)B.a * nocc + (active ? jl : 0)) * B.ng + plane_off;
+    cplx<T> pa[PT];
+    if constexpr (PF) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int n2 = r0 + t * RPI;
+            pa[t] = (active && n2 < NN) ? pa_src[(size_t)n2 * NN] : mk<T>(T(0), T(0));
+        }
+    }
+    cplx<T> acc[PT], xn[PT];
 #pragma unroll
     for (int t = 0; t < PT; ++t) acc[t] = mk<T>(T(0), T(0));
+    if (PF && q0 < q1) load_column(q0, xn);
 
     for (int q = q0; q < q1; ++q) {
         const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
-        const bool diag = B.diag && bb == B.a;
-        const bool bside = B.reuse && !diag;
-        int slot = 0;
-        bool cj = false;
-        if (diag) {
-            cj = jl < i;
-            slot = cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
-        } else {
-            slot = full_base + (bb - first_full) * nn + i * nocc + jl;
-        }
-        const cplx<T>* src = X + (size_t)slot * B.ng + plane_off;
+        const bool bside = B.reuse && !(B.diag && bb == B.a);
+        bool cj;
+        (void)slot_of(q, cj);
+        if constexpr (!PF) load_column(q, xn);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < PT; ++t) {
             const int m2 = r0 + t * RPI;
-            if (m2 < NN) tile[m2 * LNP + lane] = active ? src[(size_t)m2 * NN] : mk<T>(T(0), T(0));
+            if (m2 < NN) tile[m2 * LNP + lane] = xn[t];
+        }
+        // in flight during this pair's transform: the next pair's column, this pair's
+        // b-side orbital values and its W block
+        if (PF && q + 1 < q1) load_column(q + 1, xn);
+        const cplx<T>* ui_src = psi + ((size_t)bb * nocc + i) * B.ng + plane_off;
+        cplx<T> ui[PT];
+        if constexpr (PF) {
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                const int n2 = r0 + t * RPI;
+                ui[t] = (active && n2 < NN) ? ui_src[(size_t)n2 * NN] : mk<T>(T(0), T(0));
+            }
+        }
+        cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
+        cplx<T> wv[BPT];
+        if (PF && bside) {
+#pragma unroll
+            for (int t = 0; t < BPT; ++t) {
+                const int e = threadIdx.x + t * kPass3Threads;
+                const int n2 = e / WB, ww = e - n2 * WB;
+                wv[t] = e < BP ? wout[(size_t)n2 * NN + ww] : mk<T>(T(0), T(0));
+            }
         }
         __syncthreads();
         fft_lines<T, NN, +1, LNP, kPass3Threads>(tile, LNP, LNP, 1, tw + kMaxN);
-        const cplx<T>* pi = psi + ((size_t)bb * nocc + i) * B.ng + plane_off;
-        const cplx<T>* pa = psi + ((size_t)B.a * nocc + jl) * B.ng + plane_off;
         if (active) {
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
@@ -410,10 +456,10 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
                 if (n2 < NN) {
                     cplx<T> v = tile[n2 * LNP + lane];
                     if (cj) v.y = -v.y;
-                    const cplx<T> u = pi[(size_t)n2 * NN];
+                    const cplx<T> u = PF ? ui[t] : ui_src[(size_t)n2 * NN];
                     acc[t] = mk<T>(acc[t].x + u.x * v.x - u.y * v.y, acc[t].y + u.x * v.y + u.y * v.x);
                     if (bside) {
-                        const cplx<T> o = pa[(size_t)n2 * NN];
+                        const cplx<T> o = PF ? pa[t] : pa_src[(size_t)n2 * NN];
                         tile[n2 * LNP + lane] = mk<T>(o.x * v.x + o.y * v.y, o.y * v.x - o.x * v.y);  // o conj(v)
                     }
                 }
@@ -421,13 +467,12 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
         }
         if (bside) {
             __syncthreads();
-            cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
 #pragma unroll
             for (int t = 0; t < BPT; ++t) {
                 const int e = threadIdx.x + t * kPass3Threads;
                 if (e < BP) {
                     const int n2 = e / WB, ww = e - n2 * WB;
-                    cplx<T> sum = wout[(size_t)n2 * NN + ww];
+                    cplx<T> sum = PF ? wv[t] : wout[(size_t)n2 * NN + ww];
                     for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, tile[n2 * LNP + j * WB + ww]);
                     wout[(size_t)n2 * NN + ww] = sum;
                 }
@@ -503,7 +548,8 @@ int pair_groups(const PairBatch& B) {
 
 template <typename T>
 hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s) {
-    if (B.regfft) return launch_pass1_reg<T>(B, psi, X, s);
+    if constexpr (std::is_same_v<T, float>)
+        if (B.regfft & REGFFT_PASS1) return launch_pass1_reg(B, psi, X, s);
     const unsigned grid = (unsigned)((size_t)B.N1 * B.nslots);
     const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
     OCCRIK_DISPATCH(specialised(B),
@@ -514,7 +560,8 @@ hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, cons
 template <typename T>
 hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
                         hipStream_t s) {
-    if (B.regfft) return launch_pass2_reg<T>(B, X, parts, deriv_only, s);
+    if constexpr (std::is_same_v<T, float>)
+        if (B.regfft & REGFFT_PASS2) return launch_pass2_reg(B, X, parts, deriv_only, s);
     const unsigned grid = (unsigned)((size_t)B.N2 * pair_groups(B));
     const size_t lds = lds_plane_bytes<T>(B.N1, B.N3) + sizeof(double) * kFftThreads;
     OCCRIK_DISPATCH(specialised(B), hipLaunchKernelGGL((pass2_kernel<T, NN>), dim3(grid), dim3(kFftThreads), lds, s,
@@ -532,7 +579,8 @@ int pass3_splits(const PairBatch& B, int elem) {
 template <typename T>
 hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
                         const cplx<T>* tw, hipStream_t s) {
-    if (B.regfft && reg_pass3_ok<T>(B)) return launch_pass3_reg<T>(B, X, psi, Wpart, W, s);
+    if constexpr (std::is_same_v<T, float>)
+        if ((B.regfft & REGFFT_PASS3) && B.nocc <= 8) return launch_pass3_reg(B, X, psi, Wpart, W, s);
     const int nnv = specialised(B);
     if (nnv > 0 && B.nocc <= 16) {
         const int wb = colblock(nnv, (int)sizeof(cplx<T>));

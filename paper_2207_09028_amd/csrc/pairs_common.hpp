@@ -53,6 +53,14 @@ struct Recip {
     T b[9];
 };
 
+// truncated Coulomb, 4 pi / x^2 (1 - cos(x R_c)) as 8 pi sin^2(x R_c / 2) / x^2, in FP64:
+// x R_c reaches a few hundred radians on fine grids, beyond what FP32 phases resolve
+__device__ inline double trunc_coulomb(double x2, double rcut) {
+    if (x2 == 0.0) return 6.283185307179586476925286766559 * rcut * rcut;
+    const double sn = sin(0.5 * sqrt(x2) * rcut);
+    return 25.132741228718345907701147066236 * sn * sn / x2;
+}
+
 template <typename T>
 __device__ inline T momentum_sq(const Recip<T>& rc, double q0, double q1, double q2, int m1, int m2, int m3) {
     const T a = T(m1 + q0), b = T(m2 + q1), c = T(m3 + q2);
@@ -60,6 +68,22 @@ __device__ inline T momentum_sq(const Recip<T>& rc, double q0, double q1, double
     const T gy = a * rc.b[1] + b * rc.b[4] + c * rc.b[7];
     const T gz = a * rc.b[2] + b * rc.b[5] + c * rc.b[8];
     return gx * gx + gy * gy + gz * gz;
+}
+
+// f (or df/domega when deriv) at G_m + q, m = (m1, m2, m3) as signed frequencies
+template <typename T>
+__device__ inline T kernel_at(const PairBatch& B, const Recip<T>& rc, double q0, double q1, double q2, int m1, int m2,
+                              int m3, bool deriv, T om) {
+    if (B.kernel == OCCRIK_KERNEL_TRUNC_COULOMB) {
+        if (deriv) return T(0);
+        const double a = m1 + q0, b = m2 + q1, c = m3 + q2;
+        const double gx = a * B.recip[0] + b * B.recip[3] + c * B.recip[6];
+        const double gy = a * B.recip[1] + b * B.recip[4] + c * B.recip[7];
+        const double gz = a * B.recip[2] + b * B.recip[5] + c * B.recip[8];
+        return T(trunc_coulomb(gx * gx + gy * gy + gz * gz, B.rcut));
+    }
+    const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
+    return deriv ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
 }
 
 // Sizes: compile-time when NN > 0 (cubic NN^3 grid), else taken from the batch.

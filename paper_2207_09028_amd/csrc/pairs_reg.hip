@@ -69,24 +69,23 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass1r_kernel(PairBatch B, con
     const int nvalid = (NN - n1base < PL ? NN - n1base : PL) * PLANE;
     const size_t g0 = (size_t)n1base * PLANE;
     cplx<T> ui[IT], uj[IT];
+    static_assert(TOT % NT == 0, "a plane group is a whole number of workgroup sweeps");
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int e = threadIdx.x + it * NT;
-        if (e < nvalid) {
-            ui[it] = pi[g0 + e];
-            uj[it] = pj[g0 + e];
-        } else {
-            ui[it] = mk<T>(T(0), T(0));
-            uj[it] = ui[it];
-        }
+        // planes past the grid edge (only when PL does not divide N) read plane n1base
+        // again and are zeroed below, so every load stays in bounds without a branch
+        const int ee = (NN % PL == 0 || e < nvalid) ? e : e % PLANE;
+        ui[it] = pi[g0 + ee];
+        uj[it] = pj[g0 + ee];
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int e = threadIdx.x + it * NT;
-        if (e < TOT) {
-            const int p = e / PLANE, r = e - p * PLANE, n2 = r / NN, n3 = r - n2 * NN;
-            L[(p * NN + n2) * S + n3] = cjmul<T>(ui[it], uj[it]);
-        }
+        const int p = e / PLANE, r = e - p * PLANE, n2 = r / NN, n3 = r - n2 * NN;
+        cplx<T> u = cjmul<T>(ui[it], uj[it]);
+        if (NN % PL != 0 && e >= nvalid) u = mk<T>(T(0), T(0));
+        L[(p * NN + n2) * S + n3] = u;
     }
     __syncthreads();
     const int p = threadIdx.x / C::TPP, t = threadIdx.x - p * C::TPP, line = t >> 1, s = t & 1;
@@ -112,11 +111,45 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass1r_kernel(PairBatch B, con
 }
 
 // ---------------------------------------------------------------------------
+// kernel values of a batch: f(|G + q|) (or df/domega) for every summed k_b,
+// laid out [b - b0][m2][m1][m3] so that pass 2 reads them coalesced along m3
+// ---------------------------------------------------------------------------
+template <int NN>
+__global__ void __launch_bounds__(256) kvals_kernel(PairBatch B, float* __restrict__ out, int deriv_only) {
+    constexpr int PLANE = NN * NN;
+    const size_t total = (size_t)B.nb * NN * PLANE;
+    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
+    Recip<float> rc;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) rc.b[d] = float(B.recip[d]);
+    const float om = float(B.omega);
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int bi = (int)(e / ((size_t)NN * PLANE));
+        const int r = (int)(e - (size_t)bi * NN * PLANE);
+        const int i2 = r / PLANE, i1 = (r / NN) % NN, i3 = r % NN;
+        double qa[3], qb[3];
+        kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
+        kfrac_of(B.b0 + bi, B.M1, B.M2, B.M3, qb);
+        const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
+        const int m1 = freq(i1, NN), m2 = freq(i2, NN), m3 = freq(i3, NN);
+        float f = kernel_at<float>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
+        if (sym && ((2 * m1 == -NN) || (2 * m2 == -NN) || (2 * m3 == -NN))) {
+            const int mm1 = (2 * m1 == -NN) ? -m1 : m1;
+            const int mm2 = (2 * m2 == -NN) ? -m2 : m2;
+            const int mm3 = (2 * m3 == -NN) ? -m3 : m3;
+            f = 0.5f * (f + kernel_at<float>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
+        }
+        out[e] = f;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
-template <typename T, int NN>
-__global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cplx<T>* __restrict__ X,
+template <int NN>
+__global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cplx<float>* __restrict__ X,
                                                                 double* __restrict__ parts, int deriv_only) {
+    using T = float;
     using C = RegCfg<NN>;
     constexpr int H = C::H, S = C::S, PLANE = C::PLANE, PL = C::PL, NT = C::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -143,32 +176,9 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cpl
     }
     const int p = threadIdx.x / C::TPP, t = threadIdx.x - p * C::TPP, line = t >> 1, s = t & 1;
 
-    // kernel values at this lane's (m1, m2, m3 = line) points, shared by the whole group
-    double qa[3], qb[3];
-    kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
-    kfrac_of(b, B.M1, B.M2, B.M3, qb);
-    const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
-    const T om = T(B.omega);
-    Recip<T> rc;
-#pragma unroll
-    for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
-    const int m2 = freq(m2i, NN), m3 = freq(line, NN);
-    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
-    T v[H];
-#pragma unroll
-    for (int m = 0; m < H; ++m) {
-        const int m1 = freq(blocked_index(m, s, H), NN);
-        const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
-        T f = deriv_only ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
-        if (sym && ((2 * m1 == -NN) || (2 * m2 == -NN) || (2 * m3 == -NN))) {
-            const int mm1 = (2 * m1 == -NN) ? -m1 : m1;
-            const int mm2 = (2 * m2 == -NN) ? -m2 : m2;
-            const int mm3 = (2 * m3 == -NN) ? -m3 : m3;
-            const T x2m = momentum_sq<T>(rc, q0, q1, q2, mm1, mm2, mm3);
-            f = T(0.5) * (f + (deriv_only ? kernel_dfdw<T>(x2m, B.kernel, om) : kernel_f<T>(x2m, B.kernel, om)));
-        }
-        v[m] = f;
-    }
+    // kernel values at this lane's (m1, m2, m3 = line) points, shared by the whole group;
+    // re-read per pair (cache hits) rather than held, which keeps the kernel at 3 waves/SIMD
+    const float* kv = B.kvals + ((size_t)(b - B.b0) * NN + m2i) * PLANE + line;
     const T scale = T(B.inv_ng);
     cplx<T>* Lp = L + p * NN * S;
     double acc = 0.0;
@@ -189,16 +199,20 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cpl
         // column m3 = line along n1, straight from device memory
 #pragma unroll
         for (int a = 0; a < H; ++a) x[a] = active ? base[(size_t)(2 * a + s) * PLANE] : mk<T>(T(0), T(0));
-        line_dit<T, NN, -1>(x, s);
-        double pacc = 0.0;
+        T v[H];
 #pragma unroll
-        for (int m = 0; m < H; ++m) {
-            if (deriv_only || B.parseval)
+        for (int m = 0; m < H; ++m) v[m] = kv[blocked_index(m, s, H) * NN];
+        line_dit<T, NN, -1>(x, s);
+        if (deriv_only || B.parseval) {
+            double pacc = 0.0;
+#pragma unroll
+            for (int m = 0; m < H; ++m)
                 pacc += double(v[m]) * (double(x[m].x) * double(x[m].x) + double(x[m].y) * double(x[m].y));
-            x[m] = cscale<T>(x[m], v[m] * scale);
+            if (active) acc += wgt * pacc;
+            if (deriv_only) continue;
         }
-        if (active) acc += wgt * pacc;
-        if (deriv_only) continue;
+#pragma unroll
+        for (int m = 0; m < H; ++m) x[m] = cscale<T>(x[m], v[m] * scale);
         line_dif<T, NN, +1>(x, s);                              // back along m1: n1 = 2k + s
         __syncthreads();                                        // LDS free from the last pair
 #pragma unroll
@@ -244,12 +258,13 @@ struct P3Cfg {
 
 template <typename T, int NN, int JC>
 __global__ void __launch_bounds__((P3Cfg<T, NN, JC>::NT)) pass3r_kernel(PairBatch B, const cplx<T>* __restrict__ X,
-                                                                      const cplx<T>* __restrict__ psi,
-                                                                      cplx<T>* __restrict__ Wpart,
-                                                                      cplx<T>* __restrict__ W) {
+                                                                       const cplx<T>* __restrict__ psi,
+                                                                       cplx<T>* __restrict__ Wpart,
+                                                                       cplx<T>* __restrict__ W) {
     using C = P3Cfg<T, NN, JC>;
     constexpr int H = C::H, WB = C::WB, NCB = C::NCB, LN = C::LN, NT = C::NT;
     constexpr int PLANE = NN * NN;
+    constexpr int RW = (NN * WB + NT - 1) / NT;                 // b-side block points per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* red = reinterpret_cast<cplx<T>*>(smem_raw);         // [NN][LN] b-side products
     const int n1 = blockIdx.x % NN;
@@ -268,25 +283,45 @@ __global__ void __launch_bounds__((P3Cfg<T, NN, JC>::NT)) pass3r_kernel(PairBatc
     const int jl = line / WB, w = line - jl * WB;
     const bool active = jl < nocc;
     const size_t col = (size_t)n1 * PLANE + c0 + w;
+    // stored slot of (b, i; jl, a) for summed pair q = (b - b0) nocc + i, and whether it
+    // holds the conjugate (lower triangle of the diagonal block)
+    auto slot_of = [&](int q, bool& cj) {
+        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        cj = false;
+        if (B.diag && bb == B.a) {
+            cj = jl < i;
+            return cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
+        }
+        return full_base + (bb - first_full) * nn + i * nocc + jl;
+    };
+    auto load_line = [&](int q, cplx<T>* dst) {
+        bool cj;
+        const int slot = active ? slot_of(q, cj) : 0;
+        const cplx<T>* src = X + (size_t)slot * B.ng + col;
+#pragma unroll
+        for (int a = 0; a < H; ++a) dst[a] = active ? src[(size_t)(2 * a + s) * NN] : mk<T>(T(0), T(0));
+    };
     cplx<T> acc[H];
 #pragma unroll
     for (int m = 0; m < H; ++m) acc[m] = mk<T>(T(0), T(0));
     for (int q = q0; q < q1; ++q) {
         const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
-        const bool diag = B.diag && bb == B.a;
-        const bool bside = B.reuse && !diag;
-        int slot = 0;
-        bool cj = false;
-        if (diag) {
-            cj = jl < i;
-            slot = cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
-        } else {
-            slot = full_base + (bb - first_full) * nn + i * nocc + jl;
-        }
-        const cplx<T>* src = X + (size_t)(active ? slot : 0) * B.ng + col;
+        const bool bside = B.reuse && !(B.diag && bb == B.a);
+        bool cj;
+        (void)slot_of(q, cj);
         cplx<T> x[H];
+        load_line(q, x);
+        // this pair's b-side target block, read ahead of the reduction below
+        cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
+        cplx<T> wpre[RW];
+        if (bside) {
 #pragma unroll
-        for (int a = 0; a < H; ++a) x[a] = active ? src[(size_t)(2 * a + s) * NN] : mk<T>(T(0), T(0));
+            for (int r = 0; r < RW; ++r) {
+                const int e = threadIdx.x + r * NT;
+                const int n2 = e / WB, ww = e - n2 * WB;
+                wpre[r] = (RW * NT == NN * WB || e < NN * WB) ? wout[(size_t)n2 * NN + ww] : mk<T>(T(0), T(0));
+            }
+        }
         line_dit<T, NN, +1>(x, s);                              // along m2: n2 blocked
         const cplx<T>* pi = psi + ((size_t)bb * nocc + i) * B.ng + col;
         const cplx<T>* pa = psi + ((size_t)B.a * nocc + (active ? jl : 0)) * B.ng + col;
@@ -307,12 +342,15 @@ __global__ void __launch_bounds__((P3Cfg<T, NN, JC>::NT)) pass3r_kernel(PairBatc
         }
         if (bside) {
             __syncthreads();
-            cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
-            for (int e = threadIdx.x; e < NN * WB; e += NT) {
-                const int n2 = e / WB, ww = e - n2 * WB;
-                cplx<T> sum = wout[(size_t)n2 * NN + ww];
-                for (int jj = 0; jj < nocc; ++jj) sum = cadd<T>(sum, red[n2 * LN + jj * WB + ww]);
-                wout[(size_t)n2 * NN + ww] = sum;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int e = threadIdx.x + r * NT;
+                if (RW * NT == NN * WB || e < NN * WB) {
+                    const int n2 = e / WB, ww = e - n2 * WB;
+                    cplx<T> sum = wpre[r];
+                    for (int jj = 0; jj < nocc; ++jj) sum = cadd<T>(sum, red[n2 * LN + jj * WB + ww]);
+                    wout[(size_t)n2 * NN + ww] = sum;
+                }
             }
         }
     }
@@ -333,15 +371,6 @@ bool reg_fft_size(int n1, int n2, int n3) {
     }
 }
 
-template <>
-bool reg_pass3_ok<float>(const PairBatch& B) {
-    return B.nocc <= 8;
-}
-template <>
-bool reg_pass3_ok<double>(const PairBatch& B) {
-    return B.nocc <= 8;
-}
-
 #define OCCRIK_RDISPATCH(NNV, ...)                              \
     switch (NNV) {                                              \
         case 24: { constexpr int NN = 24; __VA_ARGS__; } break; \
@@ -352,8 +381,8 @@ bool reg_pass3_ok<double>(const PairBatch& B) {
         default: return hipErrorInvalidValue;                   \
     }
 
-template <typename T>
-hipError_t launch_pass1_reg(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, hipStream_t s) {
+hipError_t launch_pass1_reg(const PairBatch& B, const cplx<float>* psi, cplx<float>* X, hipStream_t s) {
+    using T = float;
     OCCRIK_RDISPATCH(B.N1, {
         using C = RegCfg<NN>;
         const unsigned grid = (unsigned)((size_t)B.nslots * ((NN + C::PL - 1) / C::PL));
@@ -363,20 +392,24 @@ hipError_t launch_pass1_reg(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_pass2_reg(const PairBatch& B, cplx<T>* X, double* parts, int deriv_only, hipStream_t s) {
+hipError_t launch_pass2_reg(const PairBatch& B, cplx<float>* X, double* parts, int deriv_only, hipStream_t s) {
+    using T = float;
+    if (!B.kvals) return hipErrorInvalidValue;
     OCCRIK_RDISPATCH(B.N1, {
         using C = RegCfg<NN>;
+        const size_t nv = (size_t)B.nb * NN * NN * NN;
+        const unsigned kgrid = (unsigned)std::min<size_t>((nv + 255) / 256, 8192);
+        hipLaunchKernelGGL((kvals_kernel<NN>), dim3(kgrid), dim3(256), 0, s, B, B.kvals, deriv_only);
         const unsigned grid = (unsigned)((size_t)NN * pair_groups(B));
         const size_t lds = sizeof(cplx<T>) * (size_t)C::PL * NN * C::S + sizeof(double) * C::NT;
-        hipLaunchKernelGGL((pass2r_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, X, parts, deriv_only);
+        hipLaunchKernelGGL((pass2r_kernel<NN>), dim3(grid), dim3(C::NT), lds, s, B, X, parts, deriv_only);
     });
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_pass3_reg(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
-                            hipStream_t s) {
+hipError_t launch_pass3_reg(const PairBatch& B, const cplx<float>* X, const cplx<float>* psi, cplx<float>* Wpart,
+                            cplx<float>* W, hipStream_t s) {
+    using T = float;
     if (B.nocc > 8) return hipErrorInvalidValue;
     OCCRIK_RDISPATCH(B.N1, {
         using C = P3Cfg<T, NN, 8>;
@@ -386,14 +419,5 @@ hipError_t launch_pass3_reg(const PairBatch& B, const cplx<T>* X, const cplx<T>*
     });
     return hipGetLastError();
 }
-
-template hipError_t launch_pass1_reg<float>(const PairBatch&, const cplx<float>*, cplx<float>*, hipStream_t);
-template hipError_t launch_pass1_reg<double>(const PairBatch&, const cplx<double>*, cplx<double>*, hipStream_t);
-template hipError_t launch_pass2_reg<float>(const PairBatch&, cplx<float>*, double*, int, hipStream_t);
-template hipError_t launch_pass2_reg<double>(const PairBatch&, cplx<double>*, double*, int, hipStream_t);
-template hipError_t launch_pass3_reg<float>(const PairBatch&, const cplx<float>*, const cplx<float>*, cplx<float>*,
-                                            cplx<float>*, hipStream_t);
-template hipError_t launch_pass3_reg<double>(const PairBatch&, const cplx<double>*, const cplx<double>*,
-                                             cplx<double>*, cplx<double>*, hipStream_t);
 
 }  // namespace occrik

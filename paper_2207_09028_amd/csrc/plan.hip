@@ -89,6 +89,19 @@ struct occrik_plan {
     void* Wpart = nullptr;     // [splits][nocc][ng]
     void* tw = nullptr;        // [3][kMaxN]
     double* parts = nullptr;   // [kbatch * nocc^2 * N2]
+    float* kvals = nullptr;    // [kbatch][ng] kernel values (register-FFT path only)
+    // collocation: image tables (whole plan) and per-chunk scratch
+    double4* cimg = nullptr;   // images of every shell, bucketed by image cell
+    int* cbucket = nullptr;    // [nshell][nk + 1] offsets into cimg
+    std::vector<ShellDev> cshell;
+    int maxcomp = 1;
+    int cchunk = 0;            // grid points per collocation chunk (a multiple of the contraction chunk)
+    double* cphi = nullptr;    // [maxcomp][nk][cchunk]
+    double2* cw0 = nullptr;    // [nk][cchunk]
+    double2* cw1 = nullptr;
+    bool direct = false;       // integral-direct: chi~ collocated per build, chunk by chunk, never stored
+    void* chi_ws = nullptr;    // direct: [nk][nao][cchunk] chi~ of one chunk
+    bool regfft = false;       // complex64 pair passes with register-resident transforms
     double2* Kpart = nullptr;  // [nk][nao][nocc][nchunks]
     double2* Kmi = nullptr;    // [nk][nao][nocc]
     double2* Kij = nullptr;    // [nk][nocc][nocc]
@@ -191,10 +204,12 @@ int pmod(long a, int m) {
     return (int)(r < 0 ? r + m : r);
 }
 
-template <typename T>
-occrik_status run_collocation(occrik_plan* P) {
-    hipStream_t s = P->stream;
-    const int nk = P->nk, ng = P->ng;
+// Image lists of every shell (host work, once per plan): the images T of shell
+// sh kept by the truncation rule, bucketed by image cell L = t mod M, go to the
+// device as one array with per-shell offsets, so that any range of grid points
+// can be collocated later without host work.
+occrik_status build_colloc_tables(occrik_plan* P) {
+    const int nk = P->nk;
     // cell centre and circumradius
     double c[3], rho = 0.0;
     for (int d = 0; d < 3; ++d) c[d] = 0.5 * (P->lat[d] + P->lat[3 + d] + P->lat[6 + d]);
@@ -211,29 +226,10 @@ occrik_status run_collocation(occrik_plan* P) {
     double inv[9];
     invert3(P->lat, inv);
     const int nshell = (int)P->shell_l.size();
-    int maxcomp = 1;
-    for (int l : P->shell_l) maxcomp = std::max(maxcomp, (l + 1) * (l + 2) / 2);
-
-    CollocGeom g{};
-    std::memcpy(g.lat, P->lat, sizeof(g.lat));
-    for (int d = 0; d < 3; ++d) {
-        g.N[d] = P->N[d];
-        g.M[d] = P->M[d];
-    }
-    g.nk = nk;
-    g.ng = ng;
-
-    double* phi = nullptr;
-    double2 *w0 = nullptr, *w1 = nullptr;
-    double4* dimg = nullptr;
-    int* dbucket = nullptr;
-    OCCRIK_HIP(P->alloc((void**)&phi, sizeof(double) * maxcomp * (size_t)nk * ng));
-    OCCRIK_HIP(P->alloc((void**)&w0, sizeof(double2) * (size_t)nk * ng));
-    OCCRIK_HIP(P->alloc((void**)&w1, sizeof(double2) * (size_t)nk * ng));
-    OCCRIK_HIP(P->alloc((void**)&dbucket, sizeof(int) * (nk + 1)));
-    size_t img_cap = 0;
-
-    int mu0 = 0;
+    std::vector<double4> flat;
+    std::vector<int> off((size_t)nshell * (nk + 1), 0);
+    P->cshell.assign(nshell, ShellDev{});
+    P->maxcomp = 1;
     for (int sh = 0; sh < nshell; ++sh) {
         const int l = P->shell_l[sh];
         const double alpha = P->shell_exp[sh];
@@ -262,30 +258,18 @@ occrik_status run_collocation(occrik_plan* P) {
                     const int L = (pmod(t1, P->M[0]) * P->M[1] + pmod(t2, P->M[1])) * P->M[2] + pmod(t3, P->M[2]);
                     buckets[L].push_back(make_double4(tv[0], tv[1], tv[2], 0.0));
                 }
-        std::vector<double4> flat;
-        std::vector<int> off(nk + 1, 0);
         for (int L = 0; L < nk; ++L) {
-            off[L] = (int)flat.size();
+            off[(size_t)sh * (nk + 1) + L] = (int)flat.size();
             flat.insert(flat.end(), buckets[L].begin(), buckets[L].end());
         }
-        off[nk] = (int)flat.size();
-        if (flat.size() > img_cap) {
-            OCCRIK_HIP(hipStreamSynchronize(s));
-            if (dimg) P->release(dimg);
-            img_cap = std::max<size_t>(flat.size(), 1024);
-            OCCRIK_HIP(P->alloc((void**)&dimg, sizeof(double4) * img_cap));
-        }
-        // previous shell's kernels may still read the image buffers
-        OCCRIK_HIP(hipStreamSynchronize(s));
-        if (!flat.empty())
-            OCCRIK_HIP(hipMemcpy(dimg, flat.data(), sizeof(double4) * flat.size(), hipMemcpyHostToDevice));
-        OCCRIK_HIP(hipMemcpy(dbucket, off.data(), sizeof(int) * (nk + 1), hipMemcpyHostToDevice));
+        off[(size_t)sh * (nk + 1) + nk] = (int)flat.size();
 
-        ShellDev sd{};
+        ShellDev& sd = P->cshell[sh];
         for (int d = 0; d < 3; ++d) sd.R[d] = R[d];
         sd.alpha = alpha;
         sd.l = l;
         sd.ncomp = (l + 1) * (l + 2) / 2;
+        P->maxcomp = std::max(P->maxcomp, sd.ncomp);
         int ic = 0;
         for (int a = l; a >= 0; --a)
             for (int b = l - a; b >= 0; --b) {
@@ -293,20 +277,65 @@ occrik_status run_collocation(occrik_plan* P) {
                 sd.norm[ic++] = std::pow(2.0 * alpha / M_PI, 0.75) * std::pow(4.0 * alpha, 0.5 * l) /
                                 std::sqrt(dfact(2 * a - 1) * dfact(2 * b - 1) * dfact(2 * cz - 1));
             }
-        OCCRIK_HIP(launch_colloc_fold(phi, dimg, dbucket, sd, g, s));
+    }
+    if (flat.empty()) flat.push_back(make_double4(0.0, 0.0, 0.0, 0.0));
+    OCCRIK_HIP(P->alloc((void**)&P->cimg, sizeof(double4) * flat.size()));
+    OCCRIK_HIP(P->alloc((void**)&P->cbucket, sizeof(int) * off.size()));
+    OCCRIK_HIP(hipMemcpy(P->cimg, flat.data(), sizeof(double4) * flat.size(), hipMemcpyHostToDevice));
+    OCCRIK_HIP(hipMemcpy(P->cbucket, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    return OCCRIK_OK;
+}
+
+// chi~ of every AO and k at the grid points [n0, n0 + cnt) into
+// dst[(k nao + mu) ldc + coff + t], t = n - n0; scratch sized for P->cchunk points
+template <typename T>
+occrik_status collocate_range(occrik_plan* P, int n0, int cnt, cplx<T>* dst, size_t ldc, size_t coff) {
+    hipStream_t s = P->stream;
+    CollocGeom g{};
+    std::memcpy(g.lat, P->lat, sizeof(g.lat));
+    for (int d = 0; d < 3; ++d) {
+        g.N[d] = P->N[d];
+        g.M[d] = P->M[d];
+    }
+    g.nk = P->nk;
+    g.ng = P->ng;
+    g.n0 = n0;
+    g.cnt = cnt;
+    int mu0 = 0;
+    for (size_t sh = 0; sh < P->cshell.size(); ++sh) {
+        const ShellDev& sd = P->cshell[sh];
+        OCCRIK_HIP(launch_colloc_fold(P->cphi, P->cimg, P->cbucket + sh * (P->nk + 1), sd, g, s));
         for (int cc = 0; cc < sd.ncomp; ++cc) {
             double2* res = nullptr;
-            OCCRIK_HIP(launch_colloc_kdft(phi + (size_t)cc * nk * ng, w0, w1, g, s, &res));
-            OCCRIK_HIP(launch_colloc_store<T>(res, reinterpret_cast<cplx<T>*>(P->chi), mu0 + cc, P->nao, g, s));
+            OCCRIK_HIP(launch_colloc_kdft(P->cphi + (size_t)cc * P->nk * cnt, P->cw0, P->cw1, g, s, &res));
+            OCCRIK_HIP(launch_colloc_store<T>(res, dst, mu0 + cc, P->nao, ldc, coff, g, s));
         }
         mu0 += sd.ncomp;
     }
-    OCCRIK_HIP(hipStreamSynchronize(s));
-    P->release(phi);
-    P->release(w0);
-    P->release(w1);
-    P->release(dimg);
-    P->release(dbucket);
+    return OCCRIK_OK;
+}
+
+occrik_status alloc_colloc_scratch(occrik_plan* P) {
+    OCCRIK_HIP(P->alloc((void**)&P->cphi, sizeof(double) * P->maxcomp * (size_t)P->nk * P->cchunk));
+    OCCRIK_HIP(P->alloc((void**)&P->cw0, sizeof(double2) * (size_t)P->nk * P->cchunk));
+    OCCRIK_HIP(P->alloc((void**)&P->cw1, sizeof(double2) * (size_t)P->nk * P->cchunk));
+    return OCCRIK_OK;
+}
+
+// stored mode: collocate chi~ once, chunk by chunk, then drop the scratch
+template <typename T>
+occrik_status run_collocation(occrik_plan* P) {
+    occrik_status st = alloc_colloc_scratch(P);
+    for (int n0 = 0; st == OCCRIK_OK && n0 < P->ng; n0 += P->cchunk)
+        st = collocate_range<T>(P, n0, std::min(P->cchunk, P->ng - n0), reinterpret_cast<cplx<T>*>(P->chi),
+                                (size_t)P->ng, (size_t)n0);
+    if (st != OCCRIK_OK) return st;
+    OCCRIK_HIP(hipStreamSynchronize(P->stream));
+    P->release(P->cphi);
+    P->release(P->cw0);
+    P->release(P->cw1);
+    P->cphi = nullptr;
+    P->cw0 = P->cw1 = nullptr;
     return OCCRIK_OK;
 }
 
@@ -364,11 +393,15 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     B.kernel = P->params.kernel;
     B.nyquist = P->params.nyquist;
     B.omega = P->params.omega;
+    B.rcut = std::cbrt(3.0 * double(P->nk) * P->volume / (4.0 * M_PI));
     B.inv_ng = 1.0 / P->ng;
     std::memcpy(B.recip, P->recip, sizeof(B.recip));
     B.splits = splits_for(P, nb);
     B.parseval = 0;
-    B.regfft = (!(P->params.flags & OCCRIK_FLAG_LDS_FFT) && reg_fft_size(B.N1, B.N2, B.N3)) ? 1 : 0;
+    B.regfft = !P->regfft ? 0
+               : (P->params.flags & OCCRIK_FLAG_REG_FFT_ALL) ? (REGFFT_PASS1 | REGFFT_PASS2 | REGFFT_PASS3)
+                                                              : REGFFT_DEFAULT;
+    B.kvals = P->kvals;
     return B;
 }
 
@@ -389,7 +422,17 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     }
     OCCRIK_HIP(launch_reset_flags_n(P->flags, 2 + nk, s));
     OCCRIK_HIP(launch_check_finite(dC, (size_t)nk * nao * nocc, P->flags, s));
-    OCCRIK_HIP(launch_orbitals<T>(chi, dC, psi, nk, nao, nocc, ng, P->params.precision, s));
+    if (P->direct) {
+        cplx<T>* ws = reinterpret_cast<cplx<T>*>(P->chi_ws);
+        for (int n0 = 0; n0 < ng; n0 += P->cchunk) {
+            const int cnt = std::min(P->cchunk, ng - n0);
+            const occrik_status st = collocate_range<T>(P, n0, cnt, ws, (size_t)cnt, 0);
+            if (st != OCCRIK_OK) return st;
+            OCCRIK_HIP(launch_orbitals<T>(ws, (size_t)cnt, dC, psi, nk, nao, nocc, ng, n0, cnt, P->params.precision, s));
+        }
+    } else {
+        OCCRIK_HIP(launch_orbitals<T>(chi, (size_t)ng, dC, psi, nk, nao, nocc, ng, 0, ng, P->params.precision, s));
+    }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
     OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
     int64_t launches = 1;
@@ -421,8 +464,24 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
         }
     }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[2], s));
-    OCCRIK_HIP(launch_contract<T>(chi, W, P->Kpart, P->Kmi, nk, nao, nocc, ng, P->nchunks, -P->dv / nk,
-                                  P->params.precision, s));
+    {
+        const int chunk = contract_chunk(ng, P->nchunks);
+        if (P->direct) {
+            cplx<T>* ws = reinterpret_cast<cplx<T>*>(P->chi_ws);
+            for (int n0 = 0; n0 < ng; n0 += P->cchunk) {
+                const int cnt = std::min(P->cchunk, ng - n0);
+                const occrik_status st = collocate_range<T>(P, n0, cnt, ws, (size_t)cnt, 0);
+                if (st != OCCRIK_OK) return st;
+                const int c0 = n0 / chunk, c1 = std::min(P->nchunks, (n0 + cnt + chunk - 1) / chunk);
+                OCCRIK_HIP(launch_contract_part<T>(ws, (size_t)cnt, n0, W, P->Kpart, nk, nao, nocc, ng, P->nchunks, c0,
+                                                   c1 - c0, P->params.precision, s));
+            }
+        } else {
+            OCCRIK_HIP(launch_contract_part<T>(chi, (size_t)ng, 0, W, P->Kpart, nk, nao, nocc, ng, P->nchunks, 0,
+                                               P->nchunks, P->params.precision, s));
+        }
+        OCCRIK_HIP(launch_contract_reduce(P->Kpart, P->Kmi, (size_t)nk * nao * nocc, P->nchunks, -P->dv / nk, s));
+    }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[3], s));
     if (dKmi) OCCRIK_HIP(hipMemcpyAsync(dKmi, P->Kmi, sizeof(double2) * nk * nao * nocc, hipMemcpyDeviceToDevice, s));
     OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, s));
@@ -489,13 +548,17 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
             return fail(OCCRIK_ERR_UNSUPPORTED, "grid size " + std::to_string(pr->grid[d]) + " not supported");
     }
     if (pr->nocc < 1 || pr->nocc > 16) return fail(OCCRIK_ERR_INVALID_ARG, "nocc must be 1..16");
-    if (pr->kernel < 0 || pr->kernel > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
-    if (pr->kernel != OCCRIK_KERNEL_COULOMB && !(pr->omega > 0.0 && std::isfinite(pr->omega)))
+    if (pr->kernel < 0 || pr->kernel > 3) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
+    const bool range_separated = pr->kernel == OCCRIK_KERNEL_ERF_LR || pr->kernel == OCCRIK_KERNEL_ERFC_SR;
+    if (range_separated && !(pr->omega > 0.0 && std::isfinite(pr->omega)))
         return fail(OCCRIK_ERR_INVALID_ARG, "omega must be positive for range-separated kernels");
     if (pr->nyquist < 0 || pr->nyquist > 1) return fail(OCCRIK_ERR_INVALID_ARG, "unknown nyquist mode");
     if (pr->precision < 0 || pr->precision > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown precision");
     if (!(pr->lattice_tol > 0.0 && pr->lattice_tol <= 1e-3)) return fail(OCCRIK_ERR_INVALID_ARG, "lattice_tol");
-    if (pr->flags & ~OCCRIK_FLAG_LDS_FFT) return fail(OCCRIK_ERR_INVALID_ARG, "unknown bits in flags");
+    if (pr->flags & ~(OCCRIK_FLAG_LDS_FFT | OCCRIK_FLAG_REG_FFT_ALL | OCCRIK_FLAG_DIRECT))
+        return fail(OCCRIK_ERR_INVALID_ARG, "unknown bits in flags");
+    if ((pr->flags & OCCRIK_FLAG_LDS_FFT) && (pr->flags & OCCRIK_FLAG_REG_FFT_ALL))
+        return fail(OCCRIK_ERR_INVALID_ARG, "OCCRIK_FLAG_LDS_FFT and OCCRIK_FLAG_REG_FFT_ALL exclude each other");
     if (pr->kbatch < 0) return fail(OCCRIK_ERR_INVALID_ARG, "kbatch must be >= 0");
     return OCCRIK_OK;
 }
@@ -569,7 +632,10 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     P->shell_l.assign(basis->shell_l, basis->shell_l + basis->nshell);
     P->shell_exp.assign(basis->shell_exp, basis->shell_exp + basis->nshell);
     P->nao = 0;
-    for (int l : P->shell_l) P->nao += (l + 1) * (l + 2) / 2;
+    for (int l : P->shell_l) {
+        P->nao += (l + 1) * (l + 2) / 2;
+        P->maxcomp = std::max(P->maxcomp, (l + 1) * (l + 2) / 2);
+    }
     P->nocc = params->nocc;
     if (P->nocc > P->nao) {
         delete P;
@@ -577,6 +643,8 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     }
     P->fp64 = params->precision == OCCRIK_PREC_FP64;
     P->elem = P->fp64 ? 16 : 8;
+    P->regfft = !P->fp64 && !(params->flags & OCCRIK_FLAG_LDS_FFT) &&
+                reg_fft_size(params->grid[0], params->grid[1], params->grid[2]);
 
     const int nk = P->nk, ng = P->ng, nao = P->nao, nocc = P->nocc;
     const size_t per_k = (size_t)nocc * nocc * ng * P->elem;
@@ -596,14 +664,48 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     auto A = [&](void** p, size_t bytes) {
         if (e == hipSuccess) e = P->alloc(p, bytes);
     };
-    P->bytes_chi = (size_t)nk * nao * ng * P->elem;
-    A(&P->chi, P->bytes_chi);
+    // Collocation chunk: whole partial-sum chunks of the contraction, with chi~ of a
+    // chunk for every k and AO (the direct mode's workspace) within 2 GiB, or within
+    // an eighth of mem_budget when that is smaller.
+    {
+        const int cc = contract_chunk(ng, P->nchunks);
+        const size_t per_point = (size_t)nk * nao * P->elem;
+        size_t cap = (size_t)2 << 30;
+        if (params->mem_budget != 0) cap = std::min(cap, params->mem_budget / 8);
+        const size_t q = std::max<size_t>(1, cap / (per_point * cc));
+        P->cchunk = (int)std::min<size_t>((size_t)ng, q * cc);
+    }
+    // Integral-direct (Sec. II.E, Alg. 4) when asked for, or when the stored chi~
+    // would not fit next to the other workspaces: within mem_budget when one is
+    // set, else within the device memory free now.
+    const size_t bytes_chi_stored = (size_t)nk * nao * ng * P->elem;
+    const size_t bytes_other = (size_t)nk * nocc * ng * P->elem * 2 + (size_t)P->kbatch * per_k +
+                               (size_t)P->splits * nocc * ng * P->elem + sizeof(double2) * (size_t)nk * nao * nocc *
+                               (P->nchunks + 2) + (P->regfft ? sizeof(float) * (size_t)P->kbatch * ng : 0);
+    const size_t bytes_scratch = (sizeof(double) * P->maxcomp + 2 * sizeof(double2)) * (size_t)nk * P->cchunk;
+    P->direct = (params->flags & OCCRIK_FLAG_DIRECT) != 0;
+    if (!P->direct) {
+        size_t avail = params->mem_budget;
+        if (avail == 0) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = fr;
+        }
+        if (avail != 0 && bytes_chi_stored + bytes_other + bytes_scratch > avail) P->direct = true;
+    }
+    if (P->direct) {
+        P->bytes_chi = 0;
+        A(&P->chi_ws, (size_t)nk * nao * P->cchunk * P->elem);
+    } else {
+        P->bytes_chi = bytes_chi_stored;
+        A(&P->chi, P->bytes_chi);
+    }
     A(&P->psi, (size_t)nk * nocc * ng * P->elem);
     A(&P->W, (size_t)nk * nocc * ng * P->elem);
     A(&P->X, (size_t)P->kbatch * per_k);
     A(&P->Wpart, (size_t)P->splits * nocc * ng * P->elem);
     A(&P->tw, 3 * kMaxN * P->elem);
     A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
+    if (P->regfft) A((void**)&P->kvals, sizeof(float) * (size_t)P->kbatch * ng);
     A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nocc * P->nchunks);
     A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nocc);
     A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nocc * nocc);
@@ -622,7 +724,11 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         return hip_fail(e, "flag initialisation");
     }
     st = P->fp64 ? make_twiddles<double>(P) : make_twiddles<float>(P);
-    if (st == OCCRIK_OK) st = P->fp64 ? run_collocation<double>(P) : run_collocation<float>(P);
+    if (st == OCCRIK_OK) st = build_colloc_tables(P);
+    if (st == OCCRIK_OK) {
+        if (P->direct) st = alloc_colloc_scratch(P);
+        else st = P->fp64 ? run_collocation<double>(P) : run_collocation<float>(P);
+    }
     if (st != OCCRIK_OK) {
         delete P;
         return st;
@@ -656,6 +762,8 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
     info->omega = P->params.omega;
     info->cell_volume = P->volume;
     info->bytes_chi = P->bytes_chi;
+    info->integral_direct = P->direct ? 1 : 0;
+    info->colloc_chunk = P->cchunk;
     info->bytes_workspace = P->bytes_alloc - P->bytes_chi;
     info->pair_transforms = plan_reuses_pairs(P)
                                 ? (int64_t)P->nk * (P->nk - 1) / 2 * P->nocc * P->nocc +
@@ -815,6 +923,7 @@ occrik_status occrik_copy_intermediate(occrik_plan* P, int32_t which, void* dst,
     const void* src = nullptr;
     size_t n = 0;
     if (which == 0) {
+        if (P->direct) return fail(OCCRIK_ERR_STATE, "an integral-direct plan stores no chi");
         src = P->chi;
         n = (size_t)P->nk * P->nao * P->ng;
     } else if (which == 1 || which == 2) {

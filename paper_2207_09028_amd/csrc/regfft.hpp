@@ -71,21 +71,35 @@ struct TwTable {
     }
 };
 
+// a * (wr + i wi) for a compile-time twiddle; the trivial ones (+-1, +-i) cost
+// no multiplies (without fast-math the compiler cannot drop x * 0 by itself)
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cmul_c(cplx<T> a, double wr, double wi) {
-    const T r = T(wr), i = T(wi);
     cplx<T> o;
+    if (wi == 0.0 && wr == 1.0) return a;
+    if (wi == 0.0 && wr == -1.0) {
+        o.x = -a.x; o.y = -a.y;
+        return o;
+    }
+    if (wr == 0.0 && wi == 1.0) {
+        o.x = -a.y; o.y = a.x;
+        return o;
+    }
+    if (wr == 0.0 && wi == -1.0) {
+        o.x = a.y; o.y = -a.x;
+        return o;
+    }
+    const T r = T(wr), i = T(wi);
     o.x = a.x * r - a.y * i;
     o.y = a.x * i + a.y * r;
     return o;
 }
 
 // ---------------------------------------------------------------------------
-// host/device leaf DFTs (same arithmetic as Dft<R> in fft.hpp)
+// host/device leaf DFTs
 // ---------------------------------------------------------------------------
 template <typename T, int R, int DIR>
 __host__ __device__ __forceinline__ void leaf_dft(cplx<T>* v) {
-    constexpr TwTable<R, DIR> tw{};
     if constexpr (R == 2) {
         const cplx<T> a = v[0], b = v[1];
         v[0].x = a.x + b.x; v[0].y = a.y + b.y;
@@ -102,23 +116,35 @@ __host__ __device__ __forceinline__ void leaf_dft(cplx<T>* v) {
         v[2].x = ax - cx; v[2].y = ay - cy;
         v[1].x = bx + dx; v[1].y = by + dy;
         v[3].x = bx - dx; v[3].y = by - dy;
+    } else if constexpr (R == 3) {
+        // X0 = x0 + t1, X1,2 = (x0 - t1/2) +- i DIR sin(2 pi/3) (x1 - x2), t1 = x1 + x2
+        constexpr double c = 0.86602540378443864676372317075293618 * DIR;
+        const T t1x = v[1].x + v[2].x, t1y = v[1].y + v[2].y;
+        const T t2x = v[1].x - v[2].x, t2y = v[1].y - v[2].y;
+        const T mx = v[0].x - T(0.5) * t1x, my = v[0].y - T(0.5) * t1y;
+        v[0].x = v[0].x + t1x; v[0].y = v[0].y + t1y;
+        v[1].x = mx - T(c) * t2y; v[1].y = my + T(c) * t2x;
+        v[2].x = mx + T(c) * t2y; v[2].y = my - T(c) * t2x;
     } else {
-        // small odd radices (3, 5): direct sum with compile-time twiddles
-        cplx<T> out[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            T sx = v[0].x, sy = v[0].y;
-#pragma unroll
-            for (int n = 1; n < R; ++n) {
-                const TwPair w = tw.v[(n * k) % R];
-                sx += v[n].x * T(w.re) - v[n].y * T(w.im);
-                sy += v[n].x * T(w.im) + v[n].y * T(w.re);
-            }
-            out[k].x = sx;
-            out[k].y = sy;
-        }
-#pragma unroll
-        for (int k = 0; k < R; ++k) v[k] = out[k];
+        static_assert(R == 5, "leaf radices are 2, 3, 4 and 5");
+        // pairs (1, 4) and (2, 3): cosines on the sums, DIR i sines on the differences
+        constexpr double c1 = 0.30901699437494742410229341718281906;    // cos(2 pi/5)
+        constexpr double c2 = -0.80901699437494742410229341718281906;   // cos(4 pi/5)
+        constexpr double s1 = 0.95105651629515357211643933337938214 * DIR;   // sin(2 pi/5)
+        constexpr double s2 = 0.58778525229247312916870595463907277 * DIR;   // sin(4 pi/5)
+        const T t1x = v[1].x + v[4].x, t1y = v[1].y + v[4].y;
+        const T t2x = v[2].x + v[3].x, t2y = v[2].y + v[3].y;
+        const T t3x = v[1].x - v[4].x, t3y = v[1].y - v[4].y;
+        const T t4x = v[2].x - v[3].x, t4y = v[2].y - v[3].y;
+        const T a1x = v[0].x + T(c1) * t1x + T(c2) * t2x, a1y = v[0].y + T(c1) * t1y + T(c2) * t2y;
+        const T a2x = v[0].x + T(c2) * t1x + T(c1) * t2x, a2y = v[0].y + T(c2) * t1y + T(c1) * t2y;
+        const T b1x = T(s1) * t3x + T(s2) * t4x, b1y = T(s1) * t3y + T(s2) * t4y;
+        const T b2x = T(s2) * t3x - T(s1) * t4x, b2y = T(s2) * t3y - T(s1) * t4y;
+        v[0].x = v[0].x + t1x + t2x; v[0].y = v[0].y + t1y + t2y;
+        v[1].x = a1x - b1y; v[1].y = a1y + b1x;      // a1 + i b1
+        v[4].x = a1x + b1y; v[4].y = a1y - b1x;      // a1 - i b1
+        v[2].x = a2x - b2y; v[2].y = a2y + b2x;
+        v[3].x = a2x + b2y; v[3].y = a2y - b2x;
     }
 }
 

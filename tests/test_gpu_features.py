@@ -203,3 +203,48 @@ def test_ragged_batch_equals_single_builds_bitwise():
     torch.cuda.synchronize()
     for s, K, E in zip(singles, Ks, Es):
         assert torch.equal(s["K"], K) and torch.equal(s["Ex"], E)
+
+
+# ----------------------------------------------------------------------------
+# integral-direct plans (Sec. II.E, Alg. 4): chi~ collocated per build
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32, pkg.PREC_FP32_SPLIT])
+def test_integral_direct_is_bitwise_the_stored_build(precision):
+    """Forced direct mode and the stored mode run the same per-point collocation and the
+    same partial-sum chunks of the contraction, so every output is bitwise equal."""
+    prob = W.make_problem("tiny")
+    C = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+    stored = Plan(PlanSpec.from_problem(prob, precision=precision))
+    direct = Plan(PlanSpec.from_problem(prob, precision=precision, flags=pkg.FLAG_DIRECT))
+    assert stored.query().integral_direct == 0 and direct.query().integral_direct == 1
+    assert direct.query().bytes_chi == 0
+    a = stored.build(C)
+    b = direct.build(C)
+    for key in ("K", "Kmi", "Ex"):
+        assert torch.equal(a[key], b[key]), key
+    with pytest.raises(pkg.OccrikError):
+        direct.intermediate("chi")
+
+
+def test_integral_direct_switches_on_by_memory_budget_with_several_chunks():
+    """A budget too small for the stored chi~ turns the direct mode on by itself, with
+    chunks of a budget-eighth (three collocation chunks here); the FP64 result is still
+    bitwise the stored one and matches the oracle."""
+    prob = W.make_problem("tiny")
+    Cn = W.random_coefficients(prob)
+    C = torch.from_numpy(Cn).to("cuda")
+    stored = Plan(PlanSpec.from_problem(prob, kbatch=2))
+    budget = 64 << 20
+    assert stored.query().bytes_chi + stored.query().bytes_workspace > budget
+    direct = Plan(PlanSpec.from_problem(prob, kbatch=2, mem_budget=budget))
+    info = direct.query()
+    assert info.integral_direct == 1
+    assert info.colloc_chunk < info.ng
+    assert info.bytes_chi + info.bytes_workspace <= budget
+    a = stored.build(C)
+    b = direct.build(C)
+    for key in ("K", "Kmi", "Ex"):
+        assert torch.equal(a[key], b[key]), key
+    ref = occrik.build(prob, Cn, nyquist="symmetric")
+    assert abs(float(b["Ex"][0]) - ref["Ex"]) < 1e-10 * abs(ref["Ex"])

@@ -100,14 +100,44 @@ def test_tiny_fp64_end_to_end():
         assert e < TOL64, (name, e)
 
 
-@pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45)])
-def test_range_separated_kernels_fp64(kernel, omega):
+@pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45),
+                                          (W.KERNEL_TRUNC_COULOMB, 0.0)])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_other_kernels_fp64(kernel, omega, mode):
+    """Range-separated and truncated Coulomb kernels (only the kernel multiply differs)."""
     prob = W.small_problem(kernel=kernel, omega=omega)
     C = W.random_coefficients(prob)
-    ref = oracle_result(prob, C, "symmetric")
-    plan, out = run_gpu(prob, C, "symmetric")
+    ref = oracle_result(prob, C, mode)
+    plan, out = run_gpu(prob, C, mode)
     assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+    assert rel(out["K"], ref["K"]) < TOL64
     assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+
+
+@pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45),
+                                          (W.KERNEL_TRUNC_COULOMB, 0.0)])
+def test_other_kernels_fp32_split_on_register_path(kernel, omega):
+    """24^3 complex64 plans (register pass 2 and its kernel-value table) with every kernel."""
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=5, counts=(2, 2, 1), seed=33,
+                           kernel=kernel, omega=omega)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, "symmetric")
+    _, out = run_gpu(prob, C, "symmetric", precision=pkg.PREC_FP32_SPLIT)
+    assert abs(out["Ex"][0] - ref["Ex"]) <= 1e-6
+    assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5
+
+
+def test_truncated_coulomb_isolated_gaussian_on_gpu():
+    """The oracle's exact pin run through the library: one s-Gaussian per 8 bohr cell on a
+    3x3x3 k-mesh with the truncated kernel gives E_x = -sqrt(a/pi)."""
+    alpha = 0.6
+    cell = W.cubic_cell(8.0, [(0.5, 0.5, 0.5)])
+    basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
+    prob = W.Problem("sgauss", cell, basis, (3, 3, 3), (30, 30, 30), 1, seed=0, kernel=W.KERNEL_TRUNC_COULOMB)
+    C = W.random_coefficients(prob)
+    for precision, tol in ((pkg.PREC_FP64, 1e-11), (pkg.PREC_FP32_SPLIT, 1e-6)):
+        _, out = run_gpu(prob, C, "symmetric", precision=precision)
+        assert abs(out["Ex"][0] + np.sqrt(alpha / np.pi)) < tol, precision
 
 
 def test_batched_summed_kpoints_match_unbatched():
@@ -200,22 +230,35 @@ def test_every_specialised_grid_size_fp64(n, mode):
 
 
 @pytest.mark.parametrize("n", [24, 32, 36, 40, 48])
-@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32])
+@pytest.mark.parametrize("precision", [pkg.PREC_FP32, pkg.PREC_FP32_SPLIT])
 @pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
 def test_register_and_lds_transforms_agree(n, precision, mode):
-    """The register-resident line FFTs against the LDS Stockham passes on the same plan inputs.
-
-    Both compute the same sums in a different order, so they agree to the working
-    precision's rounding: 1e-12 relative in FP64, 2e-6 relative in FP32 (a few ulps of
-    complex64 accumulated over log N butterfly levels and 8 orbitals).
-    """
+    """The register-resident line FFTs (complex64 plans) against the LDS Stockham passes
+    on the same inputs.  Both compute the same sums in a different order, so they agree
+    to complex64 rounding: 2e-6 relative (a few ulps accumulated over log N butterfly
+    levels and 8 orbitals)."""
     prob = W.small_problem(kmesh=(1, 2, 2), grid=(n, n, n), nocc=8, counts=(2, 2, 1), seed=60 + n)
     C = W.random_coefficients(prob)
-    tol = 1e-12 if precision == pkg.PREC_FP64 else 2e-6
-    p_reg, o_reg = run_gpu(prob, C, mode, precision=precision)
+    tol = 2e-6
     p_lds, o_lds = run_gpu(prob, C, mode, precision=precision, flags=pkg.FLAG_LDS_FFT)
-    w_reg = p_reg.intermediate("W").cpu().numpy()
     w_lds = p_lds.intermediate("W").cpu().numpy()
-    assert rel(w_reg, w_lds) < tol
-    assert rel(o_reg["Kmi"], o_lds["Kmi"]) < tol
-    assert abs(o_reg["Ex"][0] - o_lds["Ex"][0]) < tol * abs(o_lds["Ex"][0])
+    for flags in (0, pkg.FLAG_REG_FFT_ALL):
+        p_reg, o_reg = run_gpu(prob, C, mode, precision=precision, flags=flags)
+        w_reg = p_reg.intermediate("W").cpu().numpy()
+        assert rel(w_reg, w_lds) < tol, flags
+        assert rel(o_reg["Kmi"], o_lds["Kmi"]) < tol, flags
+        assert abs(o_reg["Ex"][0] - o_lds["Ex"][0]) < tol * abs(o_lds["Ex"][0]), flags
+
+
+@pytest.mark.parametrize("n", [24, 32, 36, 40, 48])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_register_path_fp32_split_against_oracle(n, mode):
+    """Complex64 plans on cubic grids run the register-resident passes: checked against the
+    FP64 oracle to the reduced-precision bars (|dE_x| <= 1e-6 Eh, max |dK~| <= 1e-5)."""
+    prob = W.small_problem(kmesh=(1, 2, 2), grid=(n, n, n), nocc=8, counts=(2, 2, 1), seed=80 + n)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, mode)
+    for flags in (0, pkg.FLAG_REG_FFT_ALL):
+        _, out = run_gpu(prob, C, mode, precision=pkg.PREC_FP32_SPLIT, flags=flags)
+        assert abs(out["Ex"][0] - ref["Ex"]) <= 1e-6, flags
+        assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5, flags
