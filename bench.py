@@ -57,12 +57,54 @@ def run_mode(prob, C_dev, precision, nyquist, steps, warmup, profile_level, keep
     info = plan.query()
     out = dict(seconds=dt, builds_per_s=steps / dt, ms_per_build=1e3 * dt / steps, plan_seconds=plan_s,
                Ex=float(Ex.item()), profile=prof, kbatch=info.kbatch,
-               bytes_chi=int(info.bytes_chi), bytes_workspace=int(info.bytes_workspace))
+               bytes_chi=int(info.bytes_chi), bytes_workspace=int(info.bytes_workspace),
+               pass_kernels=pass_kernel_names(info, precision))
     Kkeep = K if keep_K else None
     Kmikeep = Kmi
     plan.close()
     del plan
     return out, Kkeep, Kmikeep
+
+
+SPECIALISED = (24, 30, 32, 36, 40, 48)
+
+
+def pass_kernel_names(info, precision):
+    """Names (as rocprofv3 prints them) of the kernels that run pair passes 1, 2 and 3."""
+    from paper_2207_09028_amd import PREC_FP64
+    t = "double" if precision == PREC_FP64 else "float"
+    g = tuple(info.grid)
+    n = g[0] if g[0] == g[1] == g[2] and g[0] in SPECIALISED else 0
+    reg = int(info.reg_fft_passes)
+    jc = 8 if info.nocc <= 8 else 16
+    p1 = f"pass1r_kernel<{t}, {n}>" if reg & 1 else f"pass1_kernel<{t}, {n}>"
+    p2 = f"pass2r_kernel<{n}>" if reg & 2 else f"pass2_kernel<{t}, {n}>"
+    if reg & 4:
+        p3 = f"pass3r_kernel<{t}, {n}, 8>"
+    elif n and info.nocc <= 16:
+        p3 = f"pass3f_kernel<{t}, {n}, {jc}>"
+    else:
+        p3 = f"pass3_kernel<{t}, 0>"
+    return [p1, p2, p3]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from a committed rocprofv3 --pmc summary under
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None when no
+    summary covers it or the kernel's source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    from paper_2207_09028_amd.profiling import read_traffic
+    here = os.path.dirname(os.path.abspath(__file__))
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*pmc*.md"))):
+        t = read_traffic(path)
+        if t.get("kernel") != kernel or "source" not in t:
+            continue
+        src = os.path.join(here, t["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != t.get("source_sha256"):
+            return None
+        return float(t["hbm_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(prob, nblocks, seed=0):
@@ -96,7 +138,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--modes", default="fp64,fp32split")
     ap.add_argument("--profile-level", type=int, default=2)
-    ap.add_argument("--cpu-blocks", type=int, default=12)
+    ap.add_argument("--cpu-blocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -148,9 +190,10 @@ def main(argv=None):
     avg_ms = prof["ms_pass"][q] / nl
     bytes_per_launch = prof["bytes_pass"][q] / nl
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": f"pass{q + 1}_kernel", "achieved": round(achieved, 1),
+    kname = hr["pass_kernels"][q]
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch}
+                "traffic": measured_traffic(kname), "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch}
     cpu = None
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle sample of {a.cpu_blocks} blocks")

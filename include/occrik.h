@@ -162,6 +162,7 @@ typedef struct {
     double plan_seconds;          /* wall time of occrik_plan_create */
     int32_t integral_direct;      /* 1: chi~ collocated per build (OCCRIK_FLAG_DIRECT) */
     int32_t colloc_chunk;         /* grid points per collocation chunk */
+    int32_t reg_fft_passes;       /* bit p-1 set: pair pass p runs register-resident transforms */
 } occrik_plan_info;
 
 /* Per-phase device timings of the last build(s), from HIP events recorded on

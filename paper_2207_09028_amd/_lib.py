@@ -54,7 +54,7 @@ class PlanInfo(ctypes.Structure):
                 ("omega", c_double), ("cell_volume", c_double),
                 ("bytes_chi", c_size_t), ("bytes_workspace", c_size_t),
                 ("pair_transforms", ctypes.c_int64), ("plan_seconds", c_double),
-                ("integral_direct", c_int32), ("colloc_chunk", c_int32)]
+                ("integral_direct", c_int32), ("colloc_chunk", c_int32), ("reg_fft_passes", c_int32)]
 
 
 class Profile(ctypes.Structure):

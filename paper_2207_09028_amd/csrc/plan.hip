@@ -322,9 +322,17 @@ occrik_status alloc_colloc_scratch(occrik_plan* P) {
     return OCCRIK_OK;
 }
 
-// stored mode: collocate chi~ once, chunk by chunk, then drop the scratch
+// stored mode: collocate chi~ once, chunk by chunk, then drop the scratch.  The
+// chunks here only bound the scratch (2 GiB), so they are larger than the direct
+// mode's; every value is computed per point, so the chunking changes no result.
 template <typename T>
 occrik_status run_collocation(occrik_plan* P) {
+    {
+        const int cc = contract_chunk(P->ng, P->nchunks);
+        const size_t per_point = (sizeof(double) * P->maxcomp + 2 * sizeof(double2)) * (size_t)P->nk;
+        const size_t q = std::max<size_t>(1, ((size_t)2 << 30) / (per_point * cc));
+        P->cchunk = (int)std::min<size_t>((size_t)P->ng, q * cc);
+    }
     occrik_status st = alloc_colloc_scratch(P);
     for (int n0 = 0; st == OCCRIK_OK && n0 < P->ng; n0 += P->cchunk)
         st = collocate_range<T>(P, n0, std::min(P->cchunk, P->ng - n0), reinterpret_cast<cplx<T>*>(P->chi),
@@ -764,6 +772,7 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
     info->bytes_chi = P->bytes_chi;
     info->integral_direct = P->direct ? 1 : 0;
     info->colloc_chunk = P->cchunk;
+    info->reg_fft_passes = make_batch(P, 0, 0, 1).regfft & (P->nocc <= 8 ? ~0 : ~REGFFT_PASS3);
     info->bytes_workspace = P->bytes_alloc - P->bytes_chi;
     info->pair_transforms = plan_reuses_pairs(P)
                                 ? (int64_t)P->nk * (P->nk - 1) / 2 * P->nocc * P->nocc +

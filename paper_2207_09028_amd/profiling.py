@@ -5,7 +5,14 @@
         WRITE_SIZE counters calibrate the HBM-traffic counters of the library
         kernels (bytes counted per byte actually moved);
     python -m paper_2207_09028_amd.profiling summarize <kernel_stats.csv> [--top 12]
-        a short text table of a rocprofv3 --stats kernel summary.
+        a short text table of a rocprofv3 --stats kernel summary;
+    python -m paper_2207_09028_amd.profiling traffic --kernel NAME --source FILE \
+            <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv>
+        HBM bytes per dispatch of one kernel from two rocprofv3 --pmc runs
+        (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for
+        the plain copy above; prints "key: value" lines that bench.py reads back
+        (with the SHA-256 of the kernel's source, so a changed kernel reads as
+        unmeasured).
 """
 from __future__ import annotations
 
@@ -40,6 +47,54 @@ def summarize(path: str, top: int = 12):
               f"{100 * float(r[key_t]) / total:5.1f}%")
 
 
+def _counter_per_dispatch(path: str, counter: str, kernel: str):
+    """(mean counter value per dispatch, dispatches) over rows whose kernel name contains ``kernel``."""
+    tot, n = 0.0, 0
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter and kernel in r["Kernel_Name"]:
+            tot += float(r["Counter_Value"])
+            n += 1
+    return (tot / n if n else 0.0), n
+
+
+def _copy_scale(path: str, counter: str, nbytes: int):
+    """Bytes actually moved per counter unit (KiB) for the calibration copy."""
+    val, n = _counter_per_dispatch(path, counter, "copyBuffer")
+    if n == 0:
+        val, n = _counter_per_dispatch(path, counter, "copy")
+    return nbytes / (val * 1024.0) if val else float("nan")
+
+
+def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str,
+            copy_gib: float = 2.0):
+    import hashlib
+    nbytes = int(copy_gib * (1 << 30)) // 4 * 4
+    fs = _copy_scale(cfetch_csv, "FETCH_SIZE", nbytes)
+    ws = _copy_scale(cwrite_csv, "WRITE_SIZE", nbytes)
+    f, nf = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
+    w, nw = _counter_per_dispatch(write_csv, "WRITE_SIZE", kernel)
+    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    total = f * 1024.0 * fs + w * 1024.0 * ws
+    print(f"kernel: {kernel}")
+    print(f"source: {source}")
+    print(f"source_sha256: {sha}")
+    print(f"dispatches: {nf} {nw}")
+    print(f"fetch_size_kib_per_dispatch: {f:.1f}")
+    print(f"write_size_kib_per_dispatch: {w:.1f}")
+    print(f"fetch_scale: {fs:.4f}")
+    print(f"write_scale: {ws:.4f}")
+    print(f"hbm_bytes_per_launch: {total:.6e}")
+
+
+def read_traffic(path: str) -> dict:
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "|", "`")):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -48,9 +103,16 @@ def main(argv=None):
     s = sub.add_parser("summarize")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=12)
+    t = sub.add_parser("traffic")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--source", required=True)
+    t.add_argument("--copy-gib", type=float, default=2.0)
+    t.add_argument("csvs", nargs=4)
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy(a.gib)
+    elif a.cmd == "traffic":
+        traffic(a.kernel, a.source, *a.csvs, copy_gib=a.copy_gib)
     else:
         summarize(a.csv, a.top)
 
