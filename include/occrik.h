@@ -239,10 +239,29 @@ int32_t occrik_last_error_k(const occrik_plan *plan);
 occrik_status occrik_grad(occrik_plan *plan, double gEx, void *dgradC, double *dgradOmega);
 
 /* Ragged batch: n independent plans (different cells, bases, meshes, grids,
- * nocc) built back to back with their device buffers; per-plan arguments as in
- * occrik_build_device.  All plans must share one device and one stream. */
+ * nocc), per-plan arguments as in occrik_build_device.  All plans must share one
+ * device and one stream, and no plan may appear twice.  The builds run
+ * concurrently on four worker streams of the device (largest first, each to the
+ * least-loaded stream); the plans' stream waits for all of them, so the call is
+ * asynchronous on that stream like occrik_build_device.  Results are bitwise those
+ * of single builds.  Not thread-safe: one batch at a time per device. */
 occrik_status occrik_build_batch(int32_t n, occrik_plan *const *plans, const void *const *dC,
                                  void *const *dK, void *const *dKmi, double *const *dEx);
+
+/* The same batch recorded once as a HIP graph and replayed by occrik_batch_launch
+ * with one launch: for SCF-style loops that rebuild the same cells from the same
+ * buffers.  occrik_batch_create runs no device work; it needs the plans on a
+ * non-default stream and profiling off.  The plans and every buffer passed here
+ * must outlive the batch object; each launch reads dC and writes dK/dKmi/dEx as
+ * they are at launch time.  After create the plans count as built (occrik_grad and
+ * occrik_plan_status then refer to the latest launch).  Launches are asynchronous
+ * on the plans' stream; occrik_batch_destroy waits for that stream. */
+typedef struct occrik_batch occrik_batch;
+occrik_status occrik_batch_create(int32_t n, occrik_plan *const *plans, const void *const *dC,
+                                  void *const *dK, void *const *dKmi, double *const *dEx,
+                                  occrik_batch **out);
+occrik_status occrik_batch_launch(occrik_batch *batch);
+void occrik_batch_destroy(occrik_batch *batch);
 
 /* Profiling: level 1 records HIP events around the phases of every build on
  * the plan's stream; level 2 also brackets every pair-pass launch.

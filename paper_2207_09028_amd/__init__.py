@@ -8,13 +8,13 @@ library is missing.
 from ._lib import (KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR, KERNEL_TRUNC_COULOMB, NYQUIST_FFTFREQ, NYQUIST_SYMMETRIC,
                    PREC_FP32, PREC_FP32_SPLIT, PREC_FP64, FLAG_LDS_FFT, FLAG_REG_FFT_ALL, FLAG_DIRECT, OccrikError, LIB_PATH, load)
 
-__all__ = ["Plan", "PlanSpec", "build_batch", "ExchangeEnergy", "exchange_energy", "load", "OccrikError",
+__all__ = ["Plan", "PlanSpec", "build_batch", "BatchGraph", "ExchangeEnergy", "exchange_energy", "load", "OccrikError",
            "KERNEL_COULOMB", "KERNEL_ERF_LR", "KERNEL_ERFC_SR", "KERNEL_TRUNC_COULOMB", "NYQUIST_FFTFREQ", "NYQUIST_SYMMETRIC",
            "PREC_FP64", "PREC_FP32", "PREC_FP32_SPLIT", "FLAG_LDS_FFT", "FLAG_REG_FFT_ALL", "FLAG_DIRECT", "LIB_PATH"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "PlanSpec", "build_batch", "grid_size_supported"):
+    if name in ("Plan", "PlanSpec", "build_batch", "BatchGraph", "grid_size_supported"):
         from . import plan
         return getattr(plan, name)
     if name in ("ExchangeEnergy", "exchange_energy"):

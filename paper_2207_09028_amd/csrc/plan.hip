@@ -14,6 +14,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -491,7 +492,8 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
         OCCRIK_HIP(launch_contract_reduce(P->Kpart, P->Kmi, (size_t)nk * nao * nocc, P->nchunks, -P->dv / nk, s));
     }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[3], s));
-    if (dKmi) OCCRIK_HIP(hipMemcpyAsync(dKmi, P->Kmi, sizeof(double2) * nk * nao * nocc, hipMemcpyDeviceToDevice, s));
+    // a copy kernel rather than a memcpy, so that a captured build holds kernel nodes only
+    if (dKmi) OCCRIK_HIP(launch_scale_copy(P->Kmi, (double2*)dKmi, (size_t)nk * nao * nocc, 1.0, s));
     OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, s));
     if (dK) {
         OCCRIK_HIP(launch_xi(P->Kmi, P->L, P->Y, P->flags, nk, nao, nocc, s));
@@ -872,20 +874,174 @@ occrik_status occrik_grad(occrik_plan* P, double gEx, void* dgradC, double* dgra
     return OCCRIK_OK;
 }
 
-occrik_status occrik_build_batch(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
-                                 void* const* dKmi, double* const* dEx) {
+// ---------------------------------------------------------------------------
+// ragged batches: the builds of a batch spread over worker streams of the
+// device (fork and join on the plans' stream), either enqueued directly or
+// recorded once as a HIP graph and replayed with one launch
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kBatchStreams = 4;
+
+struct BatchStreams {
+    hipStream_t s[kBatchStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchStreams] = {};
+};
+
+std::mutex g_batch_mu;
+std::vector<BatchStreams*> g_batch_streams;   // per device ordinal; kept until the process ends
+
+// the calling thread's current device must be `device`
+hipError_t batch_streams(int device, BatchStreams** out) {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    if ((int)g_batch_streams.size() <= device) g_batch_streams.resize(device + 1, nullptr);
+    if (!g_batch_streams[device]) {
+        auto* b = new BatchStreams();
+        hipError_t e = hipSuccess;
+        for (int w = 0; w < kBatchStreams && e == hipSuccess; ++w) {
+            e = hipStreamCreateWithFlags(&b->s[w], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[w], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete b;
+            return e;
+        }
+        g_batch_streams[device] = b;
+    }
+    *out = g_batch_streams[device];
+    return hipSuccess;
+}
+
+// relative cost of one build: pair round trips (each ~ N_g log N_g) plus the two GEMMs
+double build_cost(const occrik_plan* P) {
+    const double pairs = plan_reuses_pairs(P)
+                             ? double(P->nk) * (P->nk - 1) / 2 * P->nocc * P->nocc +
+                                   double(P->nk) * P->nocc * (P->nocc + 1) / 2
+                             : double(P->nk) * P->nk * P->nocc * P->nocc;
+    return pairs * P->ng * std::log2(double(P->ng)) + 2.0 * P->nk * P->nao * P->nocc * double(P->ng);
+}
+
+occrik_status validate_batch(int32_t n, occrik_plan* const* plans, const void* const* dC) {
     if (n < 0 || (n > 0 && (!plans || !dC))) return fail(OCCRIK_ERR_INVALID_ARG, "bad batch arguments");
     for (int i = 0; i < n; ++i) {
         if (!plans[i] || !dC[i]) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C in batch");
         if (plans[i]->device != plans[0]->device || plans[i]->stream != plans[0]->stream)
             return fail(OCCRIK_ERR_INVALID_ARG, "batch plans must share device and stream");
-    }
-    for (int i = 0; i < n; ++i) {
-        occrik_status st = occrik_build_device(plans[i], dC[i], dK ? dK[i] : nullptr, dKmi ? dKmi[i] : nullptr,
-                                               dEx ? dEx[i] : nullptr);
-        if (st != OCCRIK_OK) return st;
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(OCCRIK_ERR_INVALID_ARG, "a plan appears twice in the batch");
     }
     return OCCRIK_OK;
+}
+
+// Enqueue every build of the batch: worker streams wait for the plans' stream, the
+// builds go to the least-loaded worker (largest first), the plans' stream waits
+// for every worker.  The caller has made the plans' device current.
+occrik_status enqueue_batch(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                            void* const* dKmi, double* const* dEx) {
+    hipStream_t s0 = plans[0]->stream;
+    BatchStreams* bs = nullptr;
+    OCCRIK_HIP(batch_streams(plans[0]->device, &bs));
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) cost[i] = build_cost(plans[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    double load[kBatchStreams] = {};
+    OCCRIK_HIP(hipEventRecord(bs->fork, s0));
+    for (int w = 0; w < kBatchStreams; ++w) OCCRIK_HIP(hipStreamWaitEvent(bs->s[w], bs->fork, 0));
+    occrik_status st = OCCRIK_OK;
+    for (int i : order) {
+        const int w = int(std::min_element(load, load + kBatchStreams) - load);
+        load[w] += cost[i];
+        occrik_plan* P = plans[i];
+        P->stream = bs->s[w];
+        P->last_err_k = -1;
+        st = P->fp64 ? build_impl<double>(P, (const double2*)dC[i], dK ? (double2*)dK[i] : nullptr,
+                                          dKmi ? (double2*)dKmi[i] : nullptr, dEx ? dEx[i] : nullptr)
+                     : build_impl<float>(P, (const double2*)dC[i], dK ? (double2*)dK[i] : nullptr,
+                                         dKmi ? (double2*)dKmi[i] : nullptr, dEx ? dEx[i] : nullptr);
+        P->stream = s0;
+        if (st != OCCRIK_OK) break;
+    }
+    // join even after a failed enqueue, so that the plans' stream never runs ahead of the workers
+    for (int w = 0; w < kBatchStreams; ++w) {
+        OCCRIK_HIP(hipEventRecord(bs->join[w], bs->s[w]));
+        OCCRIK_HIP(hipStreamWaitEvent(s0, bs->join[w], 0));
+    }
+    return st;
+}
+
+}  // namespace
+
+struct occrik_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~occrik_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+occrik_status occrik_build_batch(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                                 void* const* dKmi, double* const* dEx) {
+    occrik_status st = validate_batch(n, plans, dC);
+    if (st != OCCRIK_OK || n == 0) return st;
+    DeviceGuard guard(plans[0]->device);
+    return enqueue_batch(n, plans, dC, dK, dKmi, dEx);
+}
+
+occrik_status occrik_batch_create(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                                  void* const* dKmi, double* const* dEx, occrik_batch** out) {
+    if (!out) return fail(OCCRIK_ERR_INVALID_ARG, "null out");
+    *out = nullptr;
+    occrik_status st = validate_batch(n, plans, dC);
+    if (st != OCCRIK_OK) return st;
+    if (n == 0) return fail(OCCRIK_ERR_INVALID_ARG, "empty batch");
+    if (!plans[0]->stream) return fail(OCCRIK_ERR_INVALID_ARG, "recording a batch needs a non-default stream");
+    for (int i = 0; i < n; ++i)
+        if (plans[i]->profiling) return fail(OCCRIK_ERR_INVALID_ARG, "profiling must be off to record a batch");
+    DeviceGuard guard(plans[0]->device);
+    BatchStreams* bs = nullptr;
+    OCCRIK_HIP(batch_streams(plans[0]->device, &bs));    // created before the capture starts
+    auto* b = new occrik_batch();
+    b->device = plans[0]->device;
+    b->stream = plans[0]->stream;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    st = enqueue_batch(n, plans, dC, dK, dKmi, dEx);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (st != OCCRIK_OK || e != hipSuccess) {
+        delete b;
+        return st != OCCRIK_OK ? st : hip_fail(e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = b;
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_batch_launch(occrik_batch* b) {
+    if (!b) return fail(OCCRIK_ERR_INVALID_ARG, "null batch");
+    DeviceGuard guard(b->device);
+    OCCRIK_HIP(hipGraphLaunch(b->exec, b->stream));
+    return OCCRIK_OK;
+}
+
+void occrik_batch_destroy(occrik_batch* b) {
+    if (!b) return;
+    DeviceGuard guard(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
 }
 
 occrik_status occrik_set_profiling(occrik_plan* P, int32_t on) {

@@ -210,5 +210,40 @@ def build_batch(plans, Cs, Ks=None, Kmis=None, Exs=None):
     check(st)
 
 
+class BatchGraph:
+    """occrik_batch_create / occrik_batch_launch / occrik_batch_destroy: a ragged batch
+    recorded once as a HIP graph and replayed with one launch.  The plans must share a
+    non-default stream (the current one when recorded); the plans and tensors passed
+    here must stay alive while the object is used."""
+
+    def __init__(self, plans, Cs, Ks=None, Kmis=None, Exs=None):
+        lib = _lib.load()
+        n = len(plans)
+        for p in plans:
+            p._sync_stream()
+        arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x.data_ptr()) if x is not None else None for x in xs])
+        hp = (_lib.PlanP * n)(*[p._h for p in plans])
+        none = [None] * n
+        self._keep = (plans, Cs, Ks, Kmis, Exs)
+        self._h = ctypes.c_void_p()
+        check(lib.occrik_batch_create(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none),
+                                      ctypes.byref(self._h)))
+        self._lib = lib
+
+    def launch(self):
+        check(self._lib.occrik_batch_launch(self._h))
+
+    def close(self):
+        if self._h:
+            self._lib.occrik_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def grid_size_supported(n: int) -> bool:
     return bool(_lib.load().occrik_grid_size_supported(int(n)))

@@ -9,7 +9,7 @@ from oracle import collocation, occrik
 import paper_2207_09028_amd as pkg
 from paper_2207_09028_amd import OccrikError
 from paper_2207_09028_amd.autograd import exchange_energy
-from paper_2207_09028_amd.plan import Plan, PlanSpec, build_batch
+from paper_2207_09028_amd.plan import BatchGraph, Plan, PlanSpec, build_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -184,6 +184,53 @@ def test_memory_budget_too_small_reports_oom():
 # ----------------------------------------------------------------------------
 # ragged batch
 # ----------------------------------------------------------------------------
+
+def _ragged_batch(precisions=(pkg.PREC_FP32,)):
+    probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
+             W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=2, counts=(1, 1, 1), seed=2),
+             W.small_problem(kmesh=(2, 2, 1), grid=(24, 24, 24), nocc=4, counts=(2, 2, 1), seed=3),
+             W.small_problem(kmesh=(1, 1, 3), grid=(16, 15, 12), nocc=5, counts=(2, 2, 1), seed=4),
+             W.small_problem(kmesh=(2, 2, 2), grid=(20, 20, 20), nocc=3, seed=5)]
+    out = []
+    for i, p in enumerate(probs):
+        prec = precisions[i % len(precisions)]
+        out.append((p, W.random_coefficients(p), prec))
+    return out
+
+
+def test_batch_graph_replays_match_eager_builds():
+    """A ragged batch recorded as one HIP graph: every replay, with other device work and
+    synchronisations in between, reproduces the single eager builds bitwise."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        items = _ragged_batch((pkg.PREC_FP32, pkg.PREC_FP64, pkg.PREC_FP32_SPLIT))
+        plans, Cs, Ks, Kmis, Es, ref = [], [], [], [], [], []
+        for p, C, prec in items:
+            plan = Plan(PlanSpec.from_problem(p, precision=prec))
+            Ct = torch.from_numpy(C).to("cuda")
+            r = plan.build(Ct)
+            ref.append({k: v.clone() for k, v in r.items()})
+            plans.append(plan)
+            Cs.append(Ct)
+            Ks.append(torch.empty_like(r["K"]))
+            Kmis.append(torch.empty_like(r["Kmi"]))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es)
+        for rep in range(3):
+            for t in Ks + Kmis + Es:
+                t.fill_(float("nan"))
+            x = torch.randn(1 << 20, device="cuda")
+            (x * x).sum().item()                       # unrelated eager work between replays
+            graph.launch()
+            side.synchronize()
+            for i, (K, Kmi, E) in enumerate(zip(Ks, Kmis, Es)):
+                assert torch.equal(K, ref[i]["K"]), (rep, i)
+                assert torch.equal(Kmi, ref[i]["Kmi"]), (rep, i)
+                assert torch.equal(E, ref[i]["Ex"]), (rep, i)
+            for plan in plans:
+                plan.status()
+        graph.close()
+
 
 def test_ragged_batch_equals_single_builds_bitwise():
     probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
