@@ -10,16 +10,30 @@ f(x) for x = |G + q|:
                            (1/r inside a sphere of radius R_c, zero outside; the
                            sphere holds the Born-von Karman supercell's volume,
                            4 pi R_c^3 / 3 = N_k Omega; Sec. II.A, Spencer-Alavi kernel)
+  truncated long range   : erf(w r)/r inside the same sphere (eq. lrtrunc), i.e.
+                           (4 pi / x) int_0^{R_c} erf(w r) sin(x r) dr.  Eq. lrtrunc
+                           writes it with erf of complex arguments whose growth
+                           cancels against exp(-x^2/4w^2); with the Faddeeva function
+                           w(z) = exp(-z^2) erfc(-iz) the same expression reads
+                             4 pi / x^2 [exp(-x^2/4w^2) - erf(w R_c) cos(x R_c)
+                                         - exp(-w^2 R_c^2) Re(exp(-i x R_c) w(z))],
+                           z = -x/(2w) + i w R_c (upper half plane, |w(z)| <= 1),
+                           which has no cancellation.  Value at x = 0:
+                           4 pi [(R_c^2/2 - 1/(4w^2)) erf(w R_c) + R_c exp(-w^2 R_c^2)/(2 w sqrt(pi))].
+                           (The appendix's asymptotic form is not used: its middle
+                           term's sign and exponential are misprinted.)
 At x = 0 the paper inserts a finite-size constant chi; for the Coulomb and the
 long-range kernels this build sets it to zero (no Madelung shift), for the
 short-range and truncated kernels chi is the x -> 0 limit the paper prescribes.
 """
 import numpy as np
+from scipy import special
 
 COULOMB = 0
 ERF_LR = 1
 ERFC_SR = 2
 TRUNC_COULOMB = 3
+TRUNC_ERF_LR = 4
 
 
 def truncation_radius(nk, cell_volume):
@@ -47,13 +61,28 @@ def kernel_values(x2, kind, omega, rcut=None):
         x = np.sqrt(x2[nz])
         out[nz] = 8.0 * np.pi / x2[nz] * np.sin(0.5 * x * rcut) ** 2
         out[~nz] = 2.0 * np.pi * rcut * rcut
+    elif kind == TRUNC_ERF_LR:
+        x = np.sqrt(x2[nz])
+        w, R = omega, rcut
+        z = -x / (2.0 * w) + 1j * w * R
+        tail = np.real(np.exp(-1j * x * R) * special.wofz(z))
+        out[nz] = 4.0 * np.pi / x2[nz] * (np.exp(-x2[nz] / (4.0 * w * w)) - special.erf(w * R) * np.cos(x * R)
+                                          - np.exp(-w * w * R * R) * tail)
+        out[~nz] = 4.0 * np.pi * ((0.5 * R * R - 0.25 / (w * w)) * special.erf(w * R)
+                                  + R * np.exp(-w * w * R * R) / (2.0 * w * np.sqrt(np.pi)))
     else:
         raise ValueError(kind)
     return out
 
 
-def kernel_domega(x2, kind, omega):
-    """d f / d omega, with the same x = 0 convention (zero where f is zeroed)."""
+def kernel_domega(x2, kind, omega, rcut=None):
+    """d f / d omega, with the same x = 0 convention (zero where f is zeroed).
+
+    Truncated long range: (8 sqrt(pi) / x) g(x), g = int_0^{R_c} r exp(-w^2 r^2) sin(x r) dr
+    = -dI/dx for I(x) = int_0^{R_c} exp(-w^2 r^2) cos(x r) dr
+    = sqrt(pi)/(2w) [exp(-x^2/4w^2) - exp(-w^2 R_c^2) Re(exp(-i x R_c) w(z))], using
+    w'(z) = -2 z w(z) + 2i/sqrt(pi); at x = 0, 8 sqrt(pi) int_0^{R_c} r^2 exp(-w^2 r^2) dr.
+    """
     x2 = np.asarray(x2, dtype=np.float64)
     out = np.zeros_like(x2)
     nz = x2 != 0.0
@@ -65,6 +94,18 @@ def kernel_domega(x2, kind, omega):
     elif kind == ERFC_SR:
         out[nz] = -2.0 * np.pi / w3 * np.exp(-x2[nz] / (4.0 * omega * omega))
         out[~nz] = -2.0 * np.pi / w3
+    elif kind == TRUNC_ERF_LR:
+        sp = np.sqrt(np.pi)
+        w, R = omega, rcut
+        x = np.sqrt(x2[nz])
+        z = -x / (2.0 * w) + 1j * w * R
+        wz = special.wofz(z)
+        dwz = -2.0 * z * wz + 2j / sp
+        d = np.exp(-1j * x * R) * (-1j * R * wz - dwz / (2.0 * w))
+        dI = sp / (2.0 * w) * (-(x / (2.0 * w * w)) * np.exp(-x2[nz] / (4.0 * w * w))
+                               - np.exp(-w * w * R * R) * np.real(d))
+        out[nz] = -8.0 * sp / x * dI
+        out[~nz] = 8.0 * sp * (sp * special.erf(w * R) / (4.0 * w ** 3) - R * np.exp(-w * w * R * R) / (2.0 * w * w))
     else:
         raise ValueError(kind)
     return out

@@ -65,7 +65,7 @@ class Geometry:
         q = self.kfrac[k2] - self.kfrac[k1]
         if derivative:
             def fn(x2):
-                return kernels.kernel_domega(x2, kind, omega)
+                return kernels.kernel_domega(x2, kind, omega, self.rcut)
         else:
             def fn(x2):
                 return kernels.kernel_values(x2, kind, omega, self.rcut)

@@ -285,8 +285,9 @@ def test_energy_gradient_in_C_by_finite_differences(small):
     assert worst_fftfreq > 1e-8
 
 
-def test_energy_derivative_in_omega_by_finite_differences():
-    prob = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.3)
+@pytest.mark.parametrize("kind", [W.KERNEL_ERF_LR, W.KERNEL_TRUNC_ERF_LR])
+def test_energy_derivative_in_omega_by_finite_differences(kind):
+    prob = W.small_problem(kernel=kind, omega=0.3)
     C = W.random_coefficients(prob)
     chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, 1e-12)
     res = occrik.build(prob, C, chi=chi, want_k=False, domega=True)
@@ -485,3 +486,59 @@ def test_mutation_truncation_radius_without_kpoints_fails(monkeypatch):
     alpha = 0.6
     err = abs(_isolated_gaussian_exchange_truncated(8.0, 28, (3, 3, 3), alpha) + math.sqrt(alpha / math.pi))
     assert err > 1e-9
+
+
+# ----------------------------------------------------------------------------
+# Truncated long-range kernel (eq. lrtrunc): erf(w r)/r cut off at R_c
+# ----------------------------------------------------------------------------
+
+def test_truncated_long_range_kernel_matches_radial_quadrature():
+    """f(G) = (4 pi / G) int_0^{R_c} erf(w r) sin(G r) dr and f(0) = 4 pi int_0^{R_c} r erf(w r) dr,
+    by quadrature of the real-space definition (independent of the complex error function)."""
+    from scipy.integrate import quad
+    for w, rc in ((0.3, 15.8), (1.1, 3.0), (0.05, 8.0)):
+        g = np.array([0.0, 0.3, 0.7, 2.0, 5.3])
+        f = kernels.kernel_values(g * g, kernels.TRUNC_ERF_LR, w, rc)
+        for gi, fi in zip(g, f):
+            if gi == 0.0:
+                val, _ = quad(lambda r: 4.0 * math.pi * r * math.erf(w * r), 0.0, rc, limit=400)
+            else:
+                val, _ = quad(lambda r: 4.0 * math.pi * math.erf(w * r) * math.sin(gi * r) / gi, 0.0, rc,
+                              limit=2000)
+            assert abs(fi - val) < 1e-11 * max(abs(val), 1.0), (w, rc, gi, fi, val)
+
+
+def test_truncated_long_range_limits():
+    """For w R_c >> 1 the cut-off erf(w r)/r is the cut-off 1/r minus erfc(w r)/r (whose tail
+    beyond R_c is negligible), so f_trunc_LR = f_trunc_Coulomb - f_SR; d f/dw matches central
+    differences."""
+    rc = 9.0
+    x2 = np.array([0.0, 0.04, 1.3, 7.0, 40.0])
+    for w in (6.0, 60.0):
+        lr = kernels.kernel_values(x2, kernels.TRUNC_ERF_LR, w, rc)
+        co = kernels.kernel_values(x2, kernels.TRUNC_COULOMB, 0.0, rc)
+        sr = kernels.kernel_values(x2, kernels.ERFC_SR, w)
+        assert np.max(np.abs(lr - (co - sr))) < 1e-11 * np.max(np.abs(co)), w
+    w = 0.37
+    d = kernels.kernel_domega(x2, kernels.TRUNC_ERF_LR, w, rc)
+    fd = (kernels.kernel_values(x2, kernels.TRUNC_ERF_LR, w + 1e-5, rc)
+          - kernels.kernel_values(x2, kernels.TRUNC_ERF_LR, w - 1e-5, rc)) / 2e-5
+    assert np.max(np.abs(d - fd)) < 1e-6 * np.max(np.abs(d))
+
+
+def _isolated_gaussian_exchange(L, n, kmesh, kind, omega, alpha=0.6):
+    cell = W.cubic_cell(L, [(0.5, 0.5, 0.5)])
+    basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
+    prob = W.Problem("sgauss", cell, basis, kmesh, (n, n, n), 1, seed=0, kernel=kind, omega=omega)
+    C = W.random_coefficients(prob)
+    return occrik.build(prob, C, want_k=False)["Ex"]
+
+
+@pytest.mark.parametrize("L,n,kmesh", [(24.0, 64, (1, 1, 1)), (8.0, 28, (3, 3, 3))])
+def test_truncated_long_range_gives_the_isolated_attenuated_exchange(L, n, kmesh):
+    """One normalised s-Gaussian, no image inside the sphere: E_x is the attenuated self-exchange
+    -sqrt(mu/pi) with 1/mu = 1/a + 1/w^2 (the erf(w r)/r interaction of two Gaussian charges)."""
+    alpha, w = 0.6, 0.7
+    mu = 1.0 / (1.0 / alpha + 1.0 / (w * w))
+    ex = _isolated_gaussian_exchange(L, n, kmesh, kernels.TRUNC_ERF_LR, w, alpha)
+    assert abs(ex + math.sqrt(mu / math.pi)) < 1e-11

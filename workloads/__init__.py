@@ -42,6 +42,7 @@ KERNEL_COULOMB = 0
 KERNEL_ERF_LR = 1
 KERNEL_ERFC_SR = 2
 KERNEL_TRUNC_COULOMB = 3
+KERNEL_TRUNC_ERF_LR = 4
 
 
 @dataclass
