@@ -75,11 +75,16 @@ enum {
     OCCRIK_KERNEL_COULOMB = 0,    /* 4 pi / x^2;                 x = 0 term zeroed */
     OCCRIK_KERNEL_ERF_LR = 1,     /* 4 pi / x^2 exp(-x^2/4w^2);  x = 0 term zeroed */
     OCCRIK_KERNEL_ERFC_SR = 2,    /* 4 pi / x^2 (1 - exp(-x^2/4w^2)); x = 0 term pi / w^2 */
-    OCCRIK_KERNEL_TRUNC_COULOMB = 3   /* 4 pi / x^2 (1 - cos(x R_c)); x = 0 term 2 pi R_c^2.
+    OCCRIK_KERNEL_TRUNC_COULOMB = 3,  /* 4 pi / x^2 (1 - cos(x R_c)); x = 0 term 2 pi R_c^2.
                                      1/r cut off at R_c (Sec. II.A, the Spencer-Alavi kernel),
                                      with 4 pi R_c^3 / 3 = N_k Omega (the k-mesh supercell's
                                      volume).  omega is ignored; d E_x / d omega is 0.
                                      Evaluated in FP64 in every precision mode. */
+    OCCRIK_KERNEL_TRUNC_ERF_LR = 4    /* erf(w r)/r cut off at the same R_c (eq. lrtrunc), as
+                                     4 pi / x^2 [e^{-x^2/4w^2} - erf(w R_c) cos(x R_c)
+                                     - e^{-w^2 R_c^2} Re(e^{-i x R_c} w(-x/2w + i w R_c))]
+                                     with the Faddeeva function w (no overflowing terms);
+                                     x = 0 term its finite limit.  Needs omega > 0; FP64. */
 };
 
 /* Treatment of the even-N Nyquist planes in the kernel multiply.

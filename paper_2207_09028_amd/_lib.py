@@ -18,7 +18,7 @@ STATUS_NAMES = {
     4: "OCCRIK_ERR_NOT_PD", 5: "OCCRIK_ERR_NONFINITE", 6: "OCCRIK_ERR_DEVICE", 7: "OCCRIK_ERR_STATE",
 }
 
-KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR, KERNEL_TRUNC_COULOMB = 0, 1, 2, 3
+KERNEL_COULOMB, KERNEL_ERF_LR, KERNEL_ERFC_SR, KERNEL_TRUNC_COULOMB, KERNEL_TRUNC_ERF_LR = 0, 1, 2, 3, 4
 NYQUIST_FFTFREQ, NYQUIST_SYMMETRIC = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_SPLIT = 0, 1, 2
 FLAG_LDS_FFT = 1

@@ -37,7 +37,7 @@ struct PairBatch {
     int splits;               // pass-3 splits of the (b, i) sum of the a-side
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
     int regfft;               // REGFFT_PASS* bits: passes run with register-resident line FFTs
-    float* kvals;             // regfft: [nb][m2][m1][m3] kernel values of the batch (plan workspace)
+    void* kvals;              // [nb][m2][m1][m3] kernel values of the batch, working precision (plan workspace)
 };
 
 // pass-2 workgroups per m2-slab of a batch

@@ -81,6 +81,41 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
+// kernel values of a batch: f(|G+q|) (or df/domega) for every summed k_b, with the
+// Nyquist-plane mean of the symmetric mode, laid out [b - b0][m2][m1][m3] so that
+// both forms of pass 2 read them coalesced; evaluated in the working precision
+// (the truncated kernels in FP64)
+template <typename T>
+__global__ void __launch_bounds__(256) kvals_kernel(PairBatch B, T* __restrict__ out, int deriv_only) {
+    const int N1 = B.N1, N2 = B.N2, N3 = B.N3;
+    const size_t per_b = (size_t)N1 * N2 * N3;
+    const size_t total = (size_t)B.nb * per_b;
+    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
+    Recip<T> rc;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
+    const T om = T(B.omega);
+    double qa[3];
+    kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int bi = (int)(e / per_b);
+        const int r = (int)(e - (size_t)bi * per_b);
+        const int i2 = r / (N1 * N3), rem = r - i2 * (N1 * N3), i1 = rem / N3, i3 = rem - i1 * N3;
+        double qb[3];
+        kfrac_of(B.b0 + bi, B.M1, B.M2, B.M3, qb);
+        const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
+        const int m1 = freq(i1, N1), m2 = freq(i2, N2), m3 = freq(i3, N3);
+        T f = kernel_at<T>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
+        if (sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3))) {
+            const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
+            const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
+            const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
+            f = T(0.5) * (f + kernel_at<T>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
+        }
+        out[e] = f;
+    }
+}
+
 template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>* __restrict__ X,
                                                             const cplx<T>* __restrict__ twg,
@@ -115,36 +150,14 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     }
     load_twiddles<T>(tw, twg);
 
-    // kernel values of this slab, shared by every pair of the group
-    double qa[3], qb[3];
-    kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
-    kfrac_of(b, B.M1, B.M2, B.M3, qb);
-    const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
-    const T om = T(B.omega);
-    Recip<T> rc;
-#pragma unroll
-    for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
-    const int m2 = freq(m2i, N2);
-    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
+    // kernel values of this slab from the batch's table, shared by every pair of the group
     const int tile_sz = N1 * N3;
+    const T* kv = static_cast<const T*>(B.kvals) + ((size_t)(b - B.b0) * N2 + m2i) * tile_sz;
     T v[VI];
 #pragma unroll
     for (int t = 0; t < VI; ++t) {
         const int e = threadIdx.x + t * kFftThreads;
-        v[t] = T(0);
-        if (e < tile_sz) {
-            const int t1 = e / N3, t3 = e - t1 * N3;
-            const int m1 = freq(t1, N1), m3 = freq(t3, N3);
-            const bool nyq = sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3));
-            T f = kernel_at<T>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
-            if (nyq) {
-                const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
-                const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
-                const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
-                f = T(0.5) * (f + kernel_at<T>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
-            }
-            v[t] = f;
-        }
+        v[t] = e < tile_sz ? kv[e] : T(0);
     }
     const T scale = T(B.inv_ng);
     const size_t rs = (size_t)N2 * N3;
@@ -560,6 +573,14 @@ hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, cons
 template <typename T>
 hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
                         hipStream_t s) {
+    if (!B.kvals) return hipErrorInvalidValue;
+    {
+        const size_t nv = (size_t)B.nb * B.ng;
+        const unsigned kgrid = (unsigned)std::min<size_t>((nv + 255) / 256, 16384);
+        hipLaunchKernelGGL((kvals_kernel<T>), dim3(kgrid), dim3(256), 0, s, B, static_cast<T*>(B.kvals), deriv_only);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if constexpr (std::is_same_v<T, float>)
         if (B.regfft & REGFFT_PASS2) return launch_pass2_reg(B, X, parts, deriv_only, s);
     const unsigned grid = (unsigned)((size_t)B.N2 * pair_groups(B));

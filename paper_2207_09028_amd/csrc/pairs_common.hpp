@@ -1,6 +1,7 @@
 // Device helpers shared by the pair-pass kernels (LDS Stockham and register forms).
 #pragma once
 
+#include "faddeeva.hpp"
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -70,17 +71,55 @@ __device__ inline T momentum_sq(const Recip<T>& rc, double q0, double q1, double
     return gx * gx + gy * gy + gz * gz;
 }
 
+// truncated long range (erf(w r)/r cut off at R_c), and its omega derivative, in FP64:
+//   f   = 4 pi / x^2 [e^{-x^2/4w^2} - erf(w R) cos(x R) - e^{-w^2 R^2} Re(e^{-ixR} w(z))]
+//   df  = -(8 sqrt(pi) / x) I'(x),  I = sqrt(pi)/(2w) [e^{-x^2/4w^2} - e^{-w^2 R^2} Re(e^{-ixR} w(z))]
+// with z = -x/(2w) + i w R and w(z) the Faddeeva function (w' = -2 z w + 2i/sqrt(pi))
+__device__ inline double trunc_erf_lr(double x2, double om, double rcut, bool deriv) {
+    constexpr double kPi = 3.14159265358979323846264338327950288;
+    constexpr double kSqrtPi = 1.77245385090551602729816748334114518;
+    const double wr2 = om * om * rcut * rcut;
+    if (x2 == 0.0) {
+        if (deriv)
+            return 8.0 * kSqrtPi * (kSqrtPi * erf(om * rcut) / (4.0 * om * om * om) -
+                                    rcut * exp(-wr2) / (2.0 * om * om));
+        return 4.0 * kPi * ((0.5 * rcut * rcut - 0.25 / (om * om)) * erf(om * rcut) +
+                            rcut * exp(-wr2) / (2.0 * om * kSqrtPi));
+    }
+    const double x = sqrt(x2);
+    const double zr = -x / (2.0 * om), zi = om * rcut;
+    double fr, fi;
+    fad::faddeeva(zr, zi, fr, fi);
+    double sn, cs;
+    sincos(x * rcut, &sn, &cs);                 // e^{-ixR} = cs - i sn
+    const double g = exp(-x2 / (4.0 * om * om));
+    const double ew = exp(-wr2);
+    if (!deriv) {
+        const double re = cs * fr + sn * fi;    // Re(e^{-ixR} w)
+        return 4.0 * kPi / x2 * (g - erf(om * rcut) * cs - ew * re);
+    }
+    // d/dx [e^{-ixR} w(z)] = e^{-ixR} (-iR w + w'(z) (-1 / 2w))
+    const double dwr = -2.0 * (zr * fr - zi * fi), dwi = -2.0 * (zr * fi + zi * fr) + 2.0 / kSqrtPi;
+    const double ur = rcut * fi - dwr / (2.0 * om);          // -iR w - w'/(2w), real part
+    const double ui = -rcut * fr - dwi / (2.0 * om);         //                   imaginary part
+    const double dre = cs * ur + sn * ui;                    // Re(e^{-ixR} u)
+    const double dI = kSqrtPi / (2.0 * om) * (-(x / (2.0 * om * om)) * g - ew * dre);
+    return -8.0 * kSqrtPi / x * dI;
+}
+
 // f (or df/domega when deriv) at G_m + q, m = (m1, m2, m3) as signed frequencies
 template <typename T>
 __device__ inline T kernel_at(const PairBatch& B, const Recip<T>& rc, double q0, double q1, double q2, int m1, int m2,
                               int m3, bool deriv, T om) {
-    if (B.kernel == OCCRIK_KERNEL_TRUNC_COULOMB) {
-        if (deriv) return T(0);
+    if (B.kernel == OCCRIK_KERNEL_TRUNC_COULOMB || B.kernel == OCCRIK_KERNEL_TRUNC_ERF_LR) {
+        if (deriv && B.kernel == OCCRIK_KERNEL_TRUNC_COULOMB) return T(0);
         const double a = m1 + q0, b = m2 + q1, c = m3 + q2;
         const double gx = a * B.recip[0] + b * B.recip[3] + c * B.recip[6];
         const double gy = a * B.recip[1] + b * B.recip[4] + c * B.recip[7];
         const double gz = a * B.recip[2] + b * B.recip[5] + c * B.recip[8];
-        return T(trunc_coulomb(gx * gx + gy * gy + gz * gz, B.rcut));
+        const double x2 = gx * gx + gy * gy + gz * gz;
+        if (B.kernel == OCCRIK_KERNEL_TRUNC_COULOMB) return T(trunc_coulomb(x2, B.rcut));
+        return T(trunc_erf_lr(x2, B.omega, B.rcut, deriv));
     }
     const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
     return deriv ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);

@@ -11,7 +11,7 @@
 //           store X[slot][n1][m2][m3] straight from registers
 //   pass 2  slab m2 of a group of pairs sharing k_b: columns m3 loaded straight
 //           from X, FFT along n1 (DIT, blocked output), multiply by the kernel
-//           f(|G+q|)/N_g held in registers for the whole group, inverse along m1
+//           f(|G+q|)/N_g from the batch's table, inverse along m1
 //           (DIF, interleaved output), LDS transpose, inverse along m3, LDS
 //           staging for a coalesced in-place store
 //   pass 3  128-byte column blocks of x-planes: inverse along m2 of the potentials
@@ -111,39 +111,6 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass1r_kernel(PairBatch B, con
 }
 
 // ---------------------------------------------------------------------------
-// kernel values of a batch: f(|G + q|) (or df/domega) for every summed k_b,
-// laid out [b - b0][m2][m1][m3] so that pass 2 reads them coalesced along m3
-// ---------------------------------------------------------------------------
-template <int NN>
-__global__ void __launch_bounds__(256) kvals_kernel(PairBatch B, float* __restrict__ out, int deriv_only) {
-    constexpr int PLANE = NN * NN;
-    const size_t total = (size_t)B.nb * NN * PLANE;
-    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
-    Recip<float> rc;
-#pragma unroll
-    for (int d = 0; d < 9; ++d) rc.b[d] = float(B.recip[d]);
-    const float om = float(B.omega);
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-        const int bi = (int)(e / ((size_t)NN * PLANE));
-        const int r = (int)(e - (size_t)bi * NN * PLANE);
-        const int i2 = r / PLANE, i1 = (r / NN) % NN, i3 = r % NN;
-        double qa[3], qb[3];
-        kfrac_of(B.a, B.M1, B.M2, B.M3, qa);
-        kfrac_of(B.b0 + bi, B.M1, B.M2, B.M3, qb);
-        const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
-        const int m1 = freq(i1, NN), m2 = freq(i2, NN), m3 = freq(i3, NN);
-        float f = kernel_at<float>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
-        if (sym && ((2 * m1 == -NN) || (2 * m2 == -NN) || (2 * m3 == -NN))) {
-            const int mm1 = (2 * m1 == -NN) ? -m1 : m1;
-            const int mm2 = (2 * m2 == -NN) ? -m2 : m2;
-            const int mm3 = (2 * m3 == -NN) ? -m3 : m3;
-            f = 0.5f * (f + kernel_at<float>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
-        }
-        out[e] = f;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
 template <int NN>
@@ -178,7 +145,7 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cpl
 
     // kernel values at this lane's (m1, m2, m3 = line) points, shared by the whole group;
     // re-read per pair (cache hits) rather than held, which keeps the kernel at 3 waves/SIMD
-    const float* kv = B.kvals + ((size_t)(b - B.b0) * NN + m2i) * PLANE + line;
+    const float* kv = static_cast<const float*>(B.kvals) + ((size_t)(b - B.b0) * NN + m2i) * PLANE + line;
     const T scale = T(B.inv_ng);
     cplx<T>* Lp = L + p * NN * S;
     double acc = 0.0;
@@ -397,9 +364,6 @@ hipError_t launch_pass2_reg(const PairBatch& B, cplx<float>* X, double* parts, i
     if (!B.kvals) return hipErrorInvalidValue;
     OCCRIK_RDISPATCH(B.N1, {
         using C = RegCfg<NN>;
-        const size_t nv = (size_t)B.nb * NN * NN * NN;
-        const unsigned kgrid = (unsigned)std::min<size_t>((nv + 255) / 256, 8192);
-        hipLaunchKernelGGL((kvals_kernel<NN>), dim3(kgrid), dim3(256), 0, s, B, B.kvals, deriv_only);
         const unsigned grid = (unsigned)((size_t)NN * pair_groups(B));
         const size_t lds = sizeof(cplx<T>) * (size_t)C::PL * NN * C::S + sizeof(double) * C::NT;
         hipLaunchKernelGGL((pass2r_kernel<NN>), dim3(grid), dim3(C::NT), lds, s, B, X, parts, deriv_only);

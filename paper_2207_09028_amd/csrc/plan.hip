@@ -90,7 +90,7 @@ struct occrik_plan {
     void* Wpart = nullptr;     // [splits][nocc][ng]
     void* tw = nullptr;        // [3][kMaxN]
     double* parts = nullptr;   // [kbatch * nocc^2 * N2]
-    float* kvals = nullptr;    // [kbatch][ng] kernel values (register-FFT path only)
+    void* kvals = nullptr;     // [kbatch][ng] kernel values of a batch, working precision
     // collocation: image tables (whole plan) and per-chunk scratch
     double4* cimg = nullptr;   // images of every shell, bucketed by image cell
     int* cbucket = nullptr;    // [nshell][nk + 1] offsets into cimg
@@ -558,8 +558,9 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
             return fail(OCCRIK_ERR_UNSUPPORTED, "grid size " + std::to_string(pr->grid[d]) + " not supported");
     }
     if (pr->nocc < 1 || pr->nocc > 16) return fail(OCCRIK_ERR_INVALID_ARG, "nocc must be 1..16");
-    if (pr->kernel < 0 || pr->kernel > 3) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
-    const bool range_separated = pr->kernel == OCCRIK_KERNEL_ERF_LR || pr->kernel == OCCRIK_KERNEL_ERFC_SR;
+    if (pr->kernel < 0 || pr->kernel > 4) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
+    const bool range_separated = pr->kernel == OCCRIK_KERNEL_ERF_LR || pr->kernel == OCCRIK_KERNEL_ERFC_SR ||
+                                 pr->kernel == OCCRIK_KERNEL_TRUNC_ERF_LR;
     if (range_separated && !(pr->omega > 0.0 && std::isfinite(pr->omega)))
         return fail(OCCRIK_ERR_INVALID_ARG, "omega must be positive for range-separated kernels");
     if (pr->nyquist < 0 || pr->nyquist > 1) return fail(OCCRIK_ERR_INVALID_ARG, "unknown nyquist mode");
@@ -691,7 +692,7 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     const size_t bytes_chi_stored = (size_t)nk * nao * ng * P->elem;
     const size_t bytes_other = (size_t)nk * nocc * ng * P->elem * 2 + (size_t)P->kbatch * per_k +
                                (size_t)P->splits * nocc * ng * P->elem + sizeof(double2) * (size_t)nk * nao * nocc *
-                               (P->nchunks + 2) + (P->regfft ? sizeof(float) * (size_t)P->kbatch * ng : 0);
+                               (P->nchunks + 2) + P->elem / 2 * (size_t)P->kbatch * ng;
     const size_t bytes_scratch = (sizeof(double) * P->maxcomp + 2 * sizeof(double2)) * (size_t)nk * P->cchunk;
     P->direct = (params->flags & OCCRIK_FLAG_DIRECT) != 0;
     if (!P->direct) {
@@ -715,7 +716,7 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     A(&P->Wpart, (size_t)P->splits * nocc * ng * P->elem);
     A(&P->tw, 3 * kMaxN * P->elem);
     A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
-    if (P->regfft) A((void**)&P->kvals, sizeof(float) * (size_t)P->kbatch * ng);
+    A(&P->kvals, P->elem / 2 * (size_t)P->kbatch * ng);
     A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nocc * P->nchunks);
     A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nocc);
     A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nocc * nocc);

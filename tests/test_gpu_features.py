@@ -82,8 +82,9 @@ def test_gradient_in_C_is_2K_over_Nk_and_matches_finite_differences():
             assert abs(fd - an) < 1e-7 * max(1.0, abs(an)) + 1e-9
 
 
-def test_gradient_in_omega_matches_oracle_and_finite_differences():
-    prob = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.3)
+@pytest.mark.parametrize("kind", [W.KERNEL_ERF_LR, W.KERNEL_TRUNC_ERF_LR])
+def test_gradient_in_omega_matches_oracle_and_finite_differences(kind):
+    prob = W.small_problem(kernel=kind, omega=0.3)
     C = W.random_coefficients(prob)
     ref = ref_for(prob, C, domega=True)
     plan = Plan(PlanSpec.from_problem(prob))

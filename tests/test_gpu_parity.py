@@ -101,7 +101,7 @@ def test_tiny_fp64_end_to_end():
 
 
 @pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45),
-                                          (W.KERNEL_TRUNC_COULOMB, 0.0)])
+                                          (W.KERNEL_TRUNC_COULOMB, 0.0), (W.KERNEL_TRUNC_ERF_LR, 0.3)])
 @pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
 def test_other_kernels_fp64(kernel, omega, mode):
     """Range-separated and truncated Coulomb kernels (only the kernel multiply differs)."""
@@ -115,7 +115,7 @@ def test_other_kernels_fp64(kernel, omega, mode):
 
 
 @pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45),
-                                          (W.KERNEL_TRUNC_COULOMB, 0.0)])
+                                          (W.KERNEL_TRUNC_COULOMB, 0.0), (W.KERNEL_TRUNC_ERF_LR, 0.3)])
 def test_other_kernels_fp32_split_on_register_path(kernel, omega):
     """24^3 complex64 plans (register pass 2 and its kernel-value table) with every kernel."""
     prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=5, counts=(2, 2, 1), seed=33,
@@ -127,17 +127,20 @@ def test_other_kernels_fp32_split_on_register_path(kernel, omega):
     assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5
 
 
-def test_truncated_coulomb_isolated_gaussian_on_gpu():
-    """The oracle's exact pin run through the library: one s-Gaussian per 8 bohr cell on a
-    3x3x3 k-mesh with the truncated kernel gives E_x = -sqrt(a/pi)."""
+@pytest.mark.parametrize("kernel,omega", [(W.KERNEL_TRUNC_COULOMB, 0.0), (W.KERNEL_TRUNC_ERF_LR, 0.7)])
+def test_truncated_kernels_isolated_gaussian_on_gpu(kernel, omega):
+    """The oracle's exact pins run through the library: one s-Gaussian per 8 bohr cell on a
+    3x3x3 k-mesh gives E_x = -sqrt(mu/pi), mu = a for the cut-off 1/r and
+    1/mu = 1/a + 1/w^2 for the cut-off erf(w r)/r."""
     alpha = 0.6
+    mu = alpha if kernel == W.KERNEL_TRUNC_COULOMB else 1.0 / (1.0 / alpha + 1.0 / (omega * omega))
     cell = W.cubic_cell(8.0, [(0.5, 0.5, 0.5)])
     basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
-    prob = W.Problem("sgauss", cell, basis, (3, 3, 3), (30, 30, 30), 1, seed=0, kernel=W.KERNEL_TRUNC_COULOMB)
+    prob = W.Problem("sgauss", cell, basis, (3, 3, 3), (30, 30, 30), 1, seed=0, kernel=kernel, omega=omega)
     C = W.random_coefficients(prob)
     for precision, tol in ((pkg.PREC_FP64, 1e-11), (pkg.PREC_FP32_SPLIT, 1e-6)):
         _, out = run_gpu(prob, C, "symmetric", precision=precision)
-        assert abs(out["Ex"][0] + np.sqrt(alpha / np.pi)) < tol, precision
+        assert abs(out["Ex"][0] + np.sqrt(mu / np.pi)) < tol, precision
 
 
 def test_batched_summed_kpoints_match_unbatched():
