@@ -107,16 +107,16 @@ enum {
                                      and FP32 accumulation */
 };
 
-/* Plan flags (occrik_params.flags, bitwise or).  Complex64 plans (PREC_FP32,
- * PREC_FP32_SPLIT) on cubic grids with N in {24, 32, 36, 40, 48} run pass 2 of the
- * pair round trip (forward transform along n1, kernel multiply, inverse along m1
- * and m3) with each line held in the registers of a lane pair; every other pass,
- * and every FP64 plan, uses LDS Stockham transforms.  The flags change that choice
- * for cross-checks and timing; results agree to rounding. */
+/* Plan flags (occrik_params.flags, bitwise or).  The pair passes transform with
+ * LDS Stockham FFTs.  Complex64 plans (PREC_FP32, PREC_FP32_SPLIT) on cubic grids
+ * with N in {24, 32, 36, 40, 48} can instead hold each line in the registers of a
+ * lane pair (OCCRIK_FLAG_REG_FFT_ALL); results agree to rounding.  On gfx950 the
+ * LDS form with register prefetch of the next pair measured as fast or faster,
+ * so the register form is for cross-checks and timing. */
 enum {
-    OCCRIK_FLAG_LDS_FFT = 1,      /* every pair-pass transform as an LDS Stockham FFT */
-    OCCRIK_FLAG_REG_FFT_ALL = 2,  /* passes 1 and 3 in registers too (complex64, cubic grids
-                                     of the sizes above, pass 3 for nocc <= 8); not with LDS_FFT */
+    OCCRIK_FLAG_LDS_FFT = 1,      /* LDS Stockham transforms (the default; kept explicit) */
+    OCCRIK_FLAG_REG_FFT_ALL = 2,  /* register-resident transforms in all three passes
+                                     (pass 3 only for nocc <= 8); not with LDS_FFT */
     OCCRIK_FLAG_DIRECT = 4        /* integral-direct (Sec. II.E, Alg. 4): chi~ is never stored;
                                      every build collocates it chunk by chunk, once for the
                                      orbitals and once for the contraction.  The plan also

@@ -55,11 +55,11 @@ template <typename T>
 hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
                         const cplx<T>* tw, hipStream_t s);
 // register-FFT variants of the three passes (pairs_reg.hip), complex64 only;
-// pass 3 takes at most 8 occupied orbitals.  The plan turns on the passes where
-// the register form measured faster than the LDS Stockham form (pass 2: the
-// forward, kernel multiply and two inverse transforms of a slab; passes 1 and 3
-// keep the LDS form, whose radix-8/6 stages issue fewer VALU instructions).
-enum { REGFFT_PASS1 = 1, REGFFT_PASS2 = 2, REGFFT_PASS3 = 4, REGFFT_DEFAULT = REGFFT_PASS2 };
+// pass 3 takes at most 8 occupied orbitals.  Plans use them only when asked
+// (OCCRIK_FLAG_REG_FFT_ALL): with the next pair prefetched into registers, the
+// LDS Stockham passes measured as fast or faster on gfx950 (their radix-8/6
+// stages issue fewer VALU instructions, and they keep more waves resident).
+enum { REGFFT_PASS1 = 1, REGFFT_PASS2 = 2, REGFFT_PASS3 = 4, REGFFT_DEFAULT = 0 };
 bool reg_fft_size(int n1, int n2, int n3);
 hipError_t launch_pass1_reg(const PairBatch& B, const cplx<float>* psi, cplx<float>* X, hipStream_t s);
 hipError_t launch_pass2_reg(const PairBatch& B, cplx<float>* X, double* parts, int deriv_only, hipStream_t s);

@@ -162,6 +162,18 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     const T scale = T(B.inv_ng);
     const size_t rs = (size_t)N2 * N3;
     double acc = 0.0;
+    // the next pair's slab is loaded into registers while this one is transformed
+    cplx<T> xn[VI];
+    auto load_slab = [&](int sl) {
+        const cplx<T>* src = X + (size_t)sl * B.ng + (size_t)m2i * N3;
+#pragma unroll
+        for (int t = 0; t < VI; ++t) {
+            const int e = threadIdx.x + t * kFftThreads;
+            const int n1 = e / N3, m3 = e - n1 * N3;
+            xn[t] = e < tile_sz ? src[n1 * rs + m3] : mk<T>(T(0), T(0));
+        }
+    };
+    load_slab(s0);
     for (int slot = s0; slot < s1; ++slot) {
         // weight of this stored pair in the full (k, k', i, j) sum
         double wgt = 1.0;
@@ -180,9 +192,10 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
             const int e = threadIdx.x + t * kFftThreads;
             if (e < tile_sz) {
                 const int n1 = e / N3, m3 = e - n1 * N3;
-                tile[n1 * S + m3] = base[n1 * rs + m3];
+                tile[n1 * S + m3] = xn[t];
             }
         }
+        if (slot + 1 < s1) load_slab(slot + 1);
         __syncthreads();
         lines<T, NN, -1>(N1, tile, N3, S, 1, tw);
         double pacc = 0.0;

@@ -117,7 +117,7 @@ def test_other_kernels_fp64(kernel, omega, mode):
 @pytest.mark.parametrize("kernel,omega", [(W.KERNEL_ERF_LR, 0.3), (W.KERNEL_ERFC_SR, 0.45),
                                           (W.KERNEL_TRUNC_COULOMB, 0.0), (W.KERNEL_TRUNC_ERF_LR, 0.3)])
 def test_other_kernels_fp32_split_on_register_path(kernel, omega):
-    """24^3 complex64 plans (register pass 2 and its kernel-value table) with every kernel."""
+    """24^3 complex64 plans (the per-batch kernel-value table) with every kernel."""
     prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=5, counts=(2, 2, 1), seed=33,
                            kernel=kernel, omega=omega)
     C = W.random_coefficients(prob)
@@ -256,8 +256,9 @@ def test_register_and_lds_transforms_agree(n, precision, mode):
 @pytest.mark.parametrize("n", [24, 32, 36, 40, 48])
 @pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
 def test_register_path_fp32_split_against_oracle(n, mode):
-    """Complex64 plans on cubic grids run the register-resident passes: checked against the
-    FP64 oracle to the reduced-precision bars (|dE_x| <= 1e-6 Eh, max |dK~| <= 1e-5)."""
+    """Complex64 plans on cubic grids, with the LDS passes and with the register-resident
+    passes: checked against the FP64 oracle to the reduced-precision bars
+    (|dE_x| <= 1e-6 Eh, max |dK~| <= 1e-5)."""
     prob = W.small_problem(kmesh=(1, 2, 2), grid=(n, n, n), nocc=8, counts=(2, 2, 1), seed=80 + n)
     C = W.random_coefficients(prob)
     ref = oracle_result(prob, C, mode)
