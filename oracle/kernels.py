@@ -23,8 +23,14 @@ f(x) for x = |G + q|:
                            (The appendix's asymptotic form is not used: its middle
                            term's sign and exponential are misprinted.)
 At x = 0 the paper inserts a finite-size constant chi; for the Coulomb and the
-long-range kernels this build sets it to zero (no Madelung shift), for the
-short-range and truncated kernels chi is the x -> 0 limit the paper prescribes.
+long-range kernels it is zero by default, or (Madelung mode) the Madelung
+correction the paper cites without a formula: chi = N_k Omega M_s for Coulomb,
+with M_s the Madelung constant of the Born-von Karman supercell (the potential a
+unit point charge lacks from its periodic images and neutralising background,
+by Ewald summation; xi / L for a simple cubic supercell of side L), and
+chi = N_k Omega M_s - pi / w^2 for the long-range kernel (Coulomb minus the
+short-range kernel's finite x = 0 value).  For the short-range and truncated
+kernels chi is the x -> 0 limit the paper prescribes.
 """
 import numpy as np
 from scipy import special
@@ -34,6 +40,37 @@ ERF_LR = 1
 ERFC_SR = 2
 TRUNC_COULOMB = 3
 TRUNC_ERF_LR = 4
+
+
+def madelung(lattice):
+    """Madelung constant M_s > 0 of the point-charge lattice with rows ``lattice``
+    (neutralising background), by Ewald summation:
+    M_s = -[sum'_T erfc(eta |T|)/|T| + (4 pi / V) sum'_G exp(-G^2/4eta^2)/G^2
+            - 2 eta / sqrt(pi) - pi / (eta^2 V)]."""
+    from math import erfc
+    lattice = np.asarray(lattice, dtype=float)
+    vol = abs(np.linalg.det(lattice))
+    eta = np.sqrt(np.pi) / vol ** (1.0 / 3.0)
+    recip = 2.0 * np.pi * np.linalg.inv(lattice).T
+    rcut, gcut = 7.0 / eta, 14.0 * eta
+
+    def triples(rows, cut):
+        """Nonzero integer t with every |t @ rows| <= cut inside the ranges
+        (|t_d| <= cut |column d of rows^-1|)."""
+        inv = np.linalg.inv(rows)
+        n = [int(np.ceil(cut * np.linalg.norm(inv[:, d]))) + 1 for d in range(3)]
+        rng = [np.arange(-k, k + 1) for k in n]
+        t = np.stack(np.meshgrid(*rng, indexing="ij"), -1).reshape(-1, 3)
+        return t[np.any(t != 0, axis=1)]
+
+    tr = triples(lattice, rcut)
+    T = np.linalg.norm(tr @ lattice, axis=1)
+    real = sum(erfc(eta * x) / x for x in T[T <= rcut])
+    tg = triples(recip, gcut)
+    G2 = np.sum((tg @ recip) ** 2, axis=1)
+    sel = G2 <= gcut * gcut
+    rec = 4.0 * np.pi / vol * np.sum(np.exp(-G2[sel] / (4.0 * eta * eta)) / G2[sel])
+    return -(real + rec - 2.0 * eta / np.sqrt(np.pi) - np.pi / (eta * eta * vol))
 
 
 def truncation_radius(nk, cell_volume):

@@ -35,7 +35,7 @@ from . import lattice as lat_mod
 class Geometry:
     """Everything the pair loop needs that depends only on cell, mesh and grid."""
 
-    def __init__(self, cell, kmesh, grid):
+    def __init__(self, cell, kmesh, grid, madelung=False):
         self.lattice = np.asarray(cell.lattice, dtype=float)
         self.kmesh = tuple(int(x) for x in kmesh)
         self.grid = tuple(int(x) for x in grid)
@@ -49,6 +49,12 @@ class Geometry:
         self.nk = self.kfrac.shape[0]
         self.miller = lat_mod.miller_grid(self.grid)
         self.rcut = kernels.truncation_radius(self.nk, self.omega_cell)
+        # Madelung mode: G + q = 0 value of the Coulomb kernel, N_k Omega M_s of the
+        # Born-von Karman supercell (its rows M_d a_d)
+        self.g0_coulomb = None
+        if madelung:
+            sup = np.asarray(self.kmesh, dtype=float)[:, None] * self.lattice
+            self.g0_coulomb = self.nk * self.omega_cell * kernels.madelung(sup)
 
     def momentum_sq(self, q_frac, mirror=False):
         """|G_m + q|^2 over the DFT grid; ``mirror`` flips Nyquist components to +N/2."""
@@ -74,6 +80,12 @@ class Geometry:
             v = 0.5 * (v + fn(self.momentum_sq(q, mirror=True)))
         elif nyquist != "fftfreq":
             raise ValueError(nyquist)
+        if self.g0_coulomb is not None and k2 == k1 and kind in (kernels.COULOMB, kernels.ERF_LR):
+            # G = 0 is grid index 0; q = 0 exactly for k2 == k1
+            if derivative:
+                v[0] = 0.0 if kind == kernels.COULOMB else 2.0 * np.pi / omega ** 3
+            else:
+                v[0] = self.g0_coulomb - (0.0 if kind == kernels.COULOMB else np.pi / (omega * omega))
         return v.reshape(self.grid)
 
 
@@ -174,14 +186,14 @@ def assemble_projector(Kmi, Kij, S, C):
 
 
 def build(prob, C, chi=None, out_k=None, nyquist="fftfreq", want_k=True, parseval=False, domega=False,
-          kind=None, omega=None):
+          kind=None, omega=None, madelung=False):
     """The whole occ-RI-K build for ``prob`` with coefficients C[k, mu, i].
 
     Returns a dict with chi (if computed here), psi, W, Kmi, Kij, ex_terms,
     Ex (the sum of ex_terms, complete only when out_k covers every k-point), K
     (assembled, when ``want_k``), and Parseval / d omega sums when requested.
     """
-    geo = Geometry(prob.cell, prob.kmesh, prob.grid)
+    geo = Geometry(prob.cell, prob.kmesh, prob.grid, madelung=madelung)
     kind = prob.kernel if kind is None else kind
     omega = prob.omega if omega is None else omega
     if chi is None:

@@ -285,15 +285,16 @@ def test_energy_gradient_in_C_by_finite_differences(small):
     assert worst_fftfreq > 1e-8
 
 
-@pytest.mark.parametrize("kind", [W.KERNEL_ERF_LR, W.KERNEL_TRUNC_ERF_LR])
-def test_energy_derivative_in_omega_by_finite_differences(kind):
+@pytest.mark.parametrize("kind,madelung", [(W.KERNEL_ERF_LR, False), (W.KERNEL_TRUNC_ERF_LR, False),
+                                           (W.KERNEL_ERF_LR, True)])
+def test_energy_derivative_in_omega_by_finite_differences(kind, madelung):
     prob = W.small_problem(kernel=kind, omega=0.3)
     C = W.random_coefficients(prob)
     chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, 1e-12)
-    res = occrik.build(prob, C, chi=chi, want_k=False, domega=True)
+    res = occrik.build(prob, C, chi=chi, want_k=False, domega=True, madelung=madelung)
     h = 1e-4
-    ep = occrik.build(prob, C, chi=chi, want_k=False, omega=0.3 + h)["Ex"]
-    em = occrik.build(prob, C, chi=chi, want_k=False, omega=0.3 - h)["Ex"]
+    ep = occrik.build(prob, C, chi=chi, want_k=False, omega=0.3 + h, madelung=madelung)["Ex"]
+    em = occrik.build(prob, C, chi=chi, want_k=False, omega=0.3 - h, madelung=madelung)["Ex"]
     fd = (ep - em) / (2 * h)
     assert abs(fd - res["dEx_domega"]) < 1e-7 * abs(fd)
 
@@ -542,3 +543,51 @@ def test_truncated_long_range_gives_the_isolated_attenuated_exchange(L, n, kmesh
     mu = 1.0 / (1.0 / alpha + 1.0 / (w * w))
     ex = _isolated_gaussian_exchange(L, n, kmesh, kernels.TRUNC_ERF_LR, w, alpha)
     assert abs(ex + math.sqrt(mu / math.pi)) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# Madelung mode: the G + q = 0 value N_k Omega M_s of the Coulomb kernel
+# ----------------------------------------------------------------------------
+
+def test_madelung_constants_of_cubic_lattices():
+    """Ewald Madelung constants of unit point charges in a neutralising background:
+    simple cubic xi = 2.837297 / L; fcc and bcc 1.791747 and 1.791858 over the
+    Wigner-Seitz radius (textbook values)."""
+    assert abs(kernels.madelung(np.eye(3) * 7.3) * 7.3 - 2.837297479) < 1e-8
+    fcc = np.array([[0, .5, .5], [.5, 0, .5], [.5, .5, 0]]) * 3.1
+    bcc = np.array([[-.5, .5, .5], [.5, -.5, .5], [.5, .5, -.5]]) * 2.2
+    for lat, ref in ((fcc, 1.791747), (bcc, 1.791858)):
+        rws = (3.0 * abs(np.linalg.det(lat)) / (4.0 * math.pi)) ** (1.0 / 3.0)
+        assert abs(kernels.madelung(lat) * rws - ref) < 2e-6
+
+
+def test_madelung_mode_removes_the_image_term_of_an_s_gaussian():
+    """With the G = 0 term set to Omega xi / L the single s-Gaussian's E_x loses its
+    xi / 2L image term: -sqrt(a/pi) - pi / (2 a L^3) exactly."""
+    L, alpha = 18.0, 0.6
+    cell = W.cubic_cell(L, [(0.5, 0.5, 0.5)])
+    basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
+    prob = W.Problem("sgauss", cell, basis, (1, 1, 1), (60, 60, 60), 1, seed=0)
+    C = np.ones((1, 1, 1), dtype=complex)
+    ex = occrik.build(prob, C, want_k=False, madelung=True)["Ex"]
+    assert abs(ex - (-math.sqrt(alpha / math.pi) - math.pi / (2 * alpha * L ** 3))) < 1e-10
+
+
+def test_madelung_mode_kmesh_equals_gamma_supercell():
+    """The k-mesh build uses the Born-von Karman supercell's constant, the Gamma build of
+    that supercell its own: the per-cell energies agree (aliasing level)."""
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=(16, 16, 16), nocc=2, counts=(2, 1), amin=0.35, amax=0.9)
+    C = W.random_coefficients(prob)
+    e_k = occrik.build(prob, C, want_k=False, madelung=True)["Ex"]
+    sc, Csc = _supercell(prob, C)
+    e_sc = occrik.build(sc, Csc, want_k=False, madelung=True)["Ex"]
+    assert abs(e_sc / prob.nk - e_k) < 1e-9 * abs(e_k)
+
+
+def test_madelung_mode_keeps_long_plus_short_range_equal_to_coulomb(small):
+    prob, C, res = small
+    w = 0.45
+    e_sr = occrik.build(prob, C, chi=res["chi"], want_k=False, kind=kernels.ERFC_SR, omega=w)["Ex"]
+    e_lr = occrik.build(prob, C, chi=res["chi"], want_k=False, kind=kernels.ERF_LR, omega=w, madelung=True)["Ex"]
+    e_co = occrik.build(prob, C, chi=res["chi"], want_k=False, kind=kernels.COULOMB, madelung=True)["Ex"]
+    assert abs(e_sr + e_lr - e_co) < 1e-12 * abs(e_co)
