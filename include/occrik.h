@@ -117,7 +117,7 @@ enum {
     OCCRIK_FLAG_LDS_FFT = 1,      /* LDS Stockham transforms (the default; kept explicit) */
     OCCRIK_FLAG_REG_FFT_ALL = 2,  /* register-resident transforms in all three passes
                                      (pass 3 only for nocc <= 8); not with LDS_FFT */
-    OCCRIK_FLAG_DIRECT = 4        /* integral-direct (Sec. II.E, Alg. 4): chi~ is never stored;
+    OCCRIK_FLAG_DIRECT = 4,       /* integral-direct (Sec. II.E, Alg. 4): chi~ is never stored;
                                      every build collocates it chunk by chunk, once for the
                                      orbitals and once for the contraction.  The plan also
                                      switches to it by itself when the stored chi~ would not
@@ -125,6 +125,13 @@ enum {
                                      memory free at plan creation).  Its chunks hold chi~ of
                                      at most 2 GiB (or mem_budget / 8) for every k and AO.
                                      Results are bitwise those of the stored mode. */
+    OCCRIK_FLAG_MADELUNG = 8      /* G+q=0 term of the Coulomb and ERF_LR kernels from the
+                                     Madelung correction instead of zero: N_k Omega M_s for
+                                     Coulomb, M_s the Ewald Madelung constant of the k-mesh
+                                     supercell's point-charge lattice (neutralising
+                                     background), and N_k Omega M_s - pi / w^2 for ERF_LR.
+                                     The paper cites the correction without a formula; this
+                                     is the reading used (other kernels: no effect). */
 };
 
 typedef struct {

@@ -24,6 +24,7 @@ PREC_FP64, PREC_FP32, PREC_FP32_SPLIT = 0, 1, 2
 FLAG_LDS_FFT = 1
 FLAG_REG_FFT_ALL = 2
 FLAG_DIRECT = 4
+FLAG_MADELUNG = 8
 
 # every function the header declares, with (restype, argtypes)
 c_int32 = ctypes.c_int32

@@ -32,6 +32,8 @@ struct PairBatch {
     int kernel, nyquist;
     double omega;
     double rcut;              // truncated Coulomb radius R_c (4 pi R_c^3 / 3 = N_k Omega)
+    int madelung;             // 1: G+q=0 term of Coulomb / ERF_LR from g0 instead of zero
+    double g0;                // N_k Omega M_s (Madelung constant of the k-mesh supercell)
     double inv_ng;
     double recip[9];          // reciprocal vectors b_1, b_2, b_3 (rows)
     int splits;               // pass-3 splits of the (b, i) sum of the a-side

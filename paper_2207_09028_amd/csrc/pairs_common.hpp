@@ -122,6 +122,14 @@ __device__ inline T kernel_at(const PairBatch& B, const Recip<T>& rc, double q0,
         return T(trunc_erf_lr(x2, B.omega, B.rcut, deriv));
     }
     const T x2 = momentum_sq<T>(rc, q0, q1, q2, m1, m2, m3);
+    if (x2 == T(0) && B.madelung &&
+        (B.kernel == OCCRIK_KERNEL_COULOMB || B.kernel == OCCRIK_KERNEL_ERF_LR)) {
+        // Madelung mode at G + q = 0 (q = 0 exactly when k_b = k_a)
+        constexpr double kPi = 3.14159265358979323846264338327950288;
+        const double w = B.omega;
+        if (B.kernel == OCCRIK_KERNEL_COULOMB) return deriv ? T(0) : T(B.g0);
+        return deriv ? T(2.0 * kPi / (w * w * w)) : T(B.g0 - kPi / (w * w));
+    }
     return deriv ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
 }
 

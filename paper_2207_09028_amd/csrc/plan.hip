@@ -101,6 +101,7 @@ struct occrik_plan {
     double2* cw0 = nullptr;    // [nk][cchunk]
     double2* cw1 = nullptr;
     bool direct = false;       // integral-direct: chi~ collocated per build, chunk by chunk, never stored
+    double madelung_g0 = 0.0;  // Madelung mode: N_k Omega M_s of the k-mesh supercell (0: off)
     void* chi_ws = nullptr;    // direct: [nk][nao][cchunk] chi~ of one chunk
     bool regfft = false;       // complex64 pair passes with register-resident transforms
     double2* Kpart = nullptr;  // [nk][nao][nocc][nchunks]
@@ -203,6 +204,57 @@ double shell_extent(double alpha, int l, double tol) {
 int pmod(long a, int m) {
     long r = a % m;
     return (int)(r < 0 ? r + m : r);
+}
+
+// Madelung constant M_s > 0 of the point-charge lattice with rows a (bohr) in a
+// neutralising background, by Ewald summation with splitting eta = sqrt(pi) / V^(1/3):
+// M_s = -[sum'_T erfc(eta|T|)/|T| + 4 pi/V sum'_G e^{-G^2/4 eta^2}/G^2 - 2 eta/sqrt(pi) - pi/(eta^2 V)]
+double madelung_constant(const double* a) {
+    const double vol = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                                 a[2] * (a[3] * a[7] - a[4] * a[6]));
+    double inv[9];
+    invert3(a, inv);
+    double g[9];                                   // reciprocal rows 2 pi (A^{-1})^T
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) g[3 * d + e] = 2.0 * M_PI * inv[3 * e + d];
+    const double eta = std::sqrt(M_PI) / std::cbrt(vol);
+    const double rcut = 7.0 / eta, gcut = 14.0 * eta;
+    // |t_d| <= cut |column d of rows^-1| covers every |t @ rows| <= cut
+    auto range = [](const double* rows, double cut, int* n) {
+        double ri[9];
+        invert3(rows, ri);
+        for (int d = 0; d < 3; ++d)
+            n[d] = (int)std::ceil(cut * std::sqrt(ri[d] * ri[d] + ri[3 + d] * ri[3 + d] + ri[6 + d] * ri[6 + d])) + 1;
+    };
+    int nr[3], ng[3];
+    range(a, rcut, nr);
+    range(g, gcut, ng);
+    double real = 0.0, rec = 0.0;
+    for (int i = -nr[0]; i <= nr[0]; ++i)
+        for (int j = -nr[1]; j <= nr[1]; ++j)
+            for (int k = -nr[2]; k <= nr[2]; ++k) {
+                if (i == 0 && j == 0 && k == 0) continue;
+                double t2 = 0.0;
+                for (int e = 0; e < 3; ++e) {
+                    const double x = i * a[e] + j * a[3 + e] + k * a[6 + e];
+                    t2 += x * x;
+                }
+                const double t = std::sqrt(t2);
+                if (t <= rcut) real += std::erfc(eta * t) / t;
+            }
+    for (int i = -ng[0]; i <= ng[0]; ++i)
+        for (int j = -ng[1]; j <= ng[1]; ++j)
+            for (int k = -ng[2]; k <= ng[2]; ++k) {
+                if (i == 0 && j == 0 && k == 0) continue;
+                double q2 = 0.0;
+                for (int e = 0; e < 3; ++e) {
+                    const double x = i * g[e] + j * g[3 + e] + k * g[6 + e];
+                    q2 += x * x;
+                }
+                if (q2 <= gcut * gcut) rec += std::exp(-q2 / (4.0 * eta * eta)) / q2;
+            }
+    rec *= 4.0 * M_PI / vol;
+    return -(real + rec - 2.0 * eta / std::sqrt(M_PI) - M_PI / (eta * eta * vol));
 }
 
 // Image lists of every shell (host work, once per plan): the images T of shell
@@ -403,6 +455,8 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     B.nyquist = P->params.nyquist;
     B.omega = P->params.omega;
     B.rcut = std::cbrt(3.0 * double(P->nk) * P->volume / (4.0 * M_PI));
+    B.madelung = P->madelung_g0 != 0.0 ? 1 : 0;
+    B.g0 = P->madelung_g0;
     B.inv_ng = 1.0 / P->ng;
     std::memcpy(B.recip, P->recip, sizeof(B.recip));
     B.splits = splits_for(P, nb);
@@ -566,7 +620,7 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
     if (pr->nyquist < 0 || pr->nyquist > 1) return fail(OCCRIK_ERR_INVALID_ARG, "unknown nyquist mode");
     if (pr->precision < 0 || pr->precision > 2) return fail(OCCRIK_ERR_INVALID_ARG, "unknown precision");
     if (!(pr->lattice_tol > 0.0 && pr->lattice_tol <= 1e-3)) return fail(OCCRIK_ERR_INVALID_ARG, "lattice_tol");
-    if (pr->flags & ~(OCCRIK_FLAG_LDS_FFT | OCCRIK_FLAG_REG_FFT_ALL | OCCRIK_FLAG_DIRECT))
+    if (pr->flags & ~(OCCRIK_FLAG_LDS_FFT | OCCRIK_FLAG_REG_FFT_ALL | OCCRIK_FLAG_DIRECT | OCCRIK_FLAG_MADELUNG))
         return fail(OCCRIK_ERR_INVALID_ARG, "unknown bits in flags");
     if ((pr->flags & OCCRIK_FLAG_LDS_FFT) && (pr->flags & OCCRIK_FLAG_REG_FFT_ALL))
         return fail(OCCRIK_ERR_INVALID_ARG, "OCCRIK_FLAG_LDS_FFT and OCCRIK_FLAG_REG_FFT_ALL exclude each other");
@@ -631,6 +685,12 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     P->nk = P->M[0] * P->M[1] * P->M[2];
     P->ng = P->N[0] * P->N[1] * P->N[2];
     P->dv = P->volume / P->ng;
+    if (params->flags & OCCRIK_FLAG_MADELUNG) {
+        double sup[9];
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) sup[3 * d + e] = P->M[d] * P->lat[3 * d + e];
+        P->madelung_g0 = double(P->nk) * P->volume * madelung_constant(sup);
+    }
     P->natm = cell->natm;
     P->atom_cart.resize(3 * P->natm);
     for (int a = 0; a < P->natm; ++a)

@@ -79,7 +79,7 @@ def _create(**override):
     (dict(nyquist=3), 1),
     (dict(lattice_tol=0.0), 1),
     (dict(kmesh=(0, 1, 1)), 1),
-    (dict(flags=8), 1),                 # undefined flag bit
+    (dict(flags=16), 1),                # undefined flag bit
     (dict(flags=3), 1),                 # LDS_FFT and REG_FFT_ALL together
     (dict(alpha=-1.0), 1),
 ])

@@ -266,3 +266,35 @@ def test_register_path_fp32_split_against_oracle(n, mode):
         _, out = run_gpu(prob, C, mode, precision=pkg.PREC_FP32_SPLIT, flags=flags)
         assert abs(out["Ex"][0] - ref["Ex"]) <= 1e-6, flags
         assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5, flags
+
+
+@pytest.mark.parametrize("kernel,omega", [(W.KERNEL_COULOMB, 0.0), (W.KERNEL_ERF_LR, 0.3)])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_madelung_mode_against_oracle(kernel, omega, mode):
+    """OCCRIK_FLAG_MADELUNG: G + q = 0 term from the supercell's Ewald Madelung constant
+    (computed on the host by the library, by the oracle in its own code)."""
+    prob = W.small_problem(kmesh=(2, 1, 3), grid=(12, 10, 9), nocc=3, kernel=kernel, omega=omega)
+    C = W.random_coefficients(prob)
+    chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+    ref = occrik.build(prob, C, chi=chi, nyquist=mode, madelung=True,
+                       domega=kernel == W.KERNEL_ERF_LR)
+    plan, out = run_gpu(prob, C, mode, flags=pkg.FLAG_MADELUNG)
+    assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+    assert rel(out["K"], ref["K"]) < TOL64
+    assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+    if kernel == W.KERNEL_ERF_LR and mode == "symmetric":
+        _, dw = plan.grad(1.0, want_C=False, want_omega=True)
+        assert abs(dw - ref["dEx_domega"]) < TOL64 * abs(ref["dEx_domega"])
+
+
+def test_madelung_mode_s_gaussian_closed_form_on_gpu():
+    """-sqrt(a/pi) - pi/(2 a L^3): the image term xi / 2L removed by the Madelung G = 0 value."""
+    L, alpha = 18.0, 0.6
+    cell = W.cubic_cell(L, [(0.5, 0.5, 0.5)])
+    basis = W.Basis(np.zeros(1, np.int32), np.zeros(1, np.int32), np.array([alpha]))
+    prob = W.Problem("sgauss", cell, basis, (1, 1, 1), (60, 60, 60), 1, seed=0)
+    C = np.ones((1, 1, 1), dtype=complex)
+    exact = -np.sqrt(alpha / np.pi) - np.pi / (2 * alpha * L ** 3)
+    for precision, tol in ((pkg.PREC_FP64, 1e-10), (pkg.PREC_FP32_SPLIT, 1e-6)):
+        _, out = run_gpu(prob, C, "symmetric", precision=precision, flags=pkg.FLAG_MADELUNG)
+        assert abs(out["Ex"][0] - exact) < tol, precision
