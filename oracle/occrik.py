@@ -114,30 +114,38 @@ def pair_potentials(geo, rho, k2, k1, kind, omega, nyquist="fftfreq", want_parse
     return V, np.sum(v * np.abs(uhat) ** 2, axis=(-3, -2, -1))
 
 
-def exchange_w(geo, psi, out_k, kind, omega, nyquist="fftfreq", parseval=False, domega=False, k1_subset=None):
+def exchange_w(geo, psi, out_k, kind, omega, nyquist="fftfreq", parseval=False, domega=False, k1_subset=None,
+               nsum=None):
     """Alg. 3 loops: W[k2][j] = sum_{k1, i} psi_{i k1} V_{i k1, j k2} for k2 in out_k.
 
-    Also returns the Parseval partial sums sum f |u^|^2 (and sum df/dw |u^|^2) over
-    the same pairs, when requested.  ``k1_subset`` restricts the summed k-points
-    (a partial sum, used only to time a bounded sample of the loops).
+    The sum runs over the first ``nsum`` orbitals of psi (the occupied ones; all by
+    default); W is formed for every orbital j of psi at k2, which with extra columns
+    is the conduction-band extension of Sec. II.D (exchange still built from the
+    occupied density).  Also returns the Parseval partial sums sum f |u^|^2 (and
+    sum df/dw |u^|^2) over the occupied pairs, when requested.  ``k1_subset``
+    restricts the summed k-points (a partial sum, used only to time a bounded
+    sample of the loops).
     """
-    nocc = psi.shape[1]
-    W = np.zeros((len(out_k), nocc, geo.ng), dtype=np.complex128)
+    nout = psi.shape[1]
+    nsum = nout if nsum is None else nsum
+    W = np.zeros((len(out_k), nout, geo.ng), dtype=np.complex128)
     ps = 0.0
     pd = 0.0
     k1_list = range(geo.nk) if k1_subset is None else list(k1_subset)
     for a, k2 in enumerate(out_k):
-        for j in range(nocc):
+        for j in range(nout):
+            occ_pair = j < nsum
             for k1 in k1_list:
-                rho = np.conj(psi[k1]) * psi[k2, j][None, :]          # all i at once
-                V, s = pair_potentials(geo, rho, k2, k1, kind, omega, nyquist, want_parseval=parseval or domega)
-                W[a, j] += np.sum(psi[k1] * V, axis=0)
-                if parseval:
+                rho = np.conj(psi[k1, :nsum]) * psi[k2, j][None, :]    # all summed i at once
+                V, s = pair_potentials(geo, rho, k2, k1, kind, omega, nyquist,
+                                       want_parseval=occ_pair and (parseval or domega))
+                W[a, j] += np.sum(psi[k1, :nsum] * V, axis=0)
+                if parseval and occ_pair:
                     ps += float(np.sum(s))
-                if domega:
+                if domega and occ_pair:
                     qc = geo.kcart[k2] - geo.kcart[k1]
                     ph = np.exp(-1j * (geo.r @ qc))
-                    uhat = np.fft.fftn((rho * ph).reshape((nocc,) + geo.grid), axes=(-3, -2, -1))
+                    uhat = np.fft.fftn((rho * ph).reshape((nsum,) + geo.grid), axes=(-3, -2, -1))
                     dv = geo.kernel_on_grid(k2, k1, kind, omega, nyquist, derivative=True)
                     pd += float(np.sum(dv * np.abs(uhat) ** 2))
     return W, ps, pd
@@ -153,9 +161,11 @@ def occupied_block(C_out, Kmi):
     return np.einsum("kmi,kmj->kij", np.conj(C_out), Kmi)
 
 
-def exchange_energy_terms(Kij, nk):
-    """Per-k contributions Re tr K_ij(k) / (2 N_k); their sum over all k is E_x."""
-    return np.real(np.einsum("kii->k", Kij)) / (2.0 * nk)
+def exchange_energy_terms(Kij, nk, nocc=None):
+    """Per-k contributions Re tr K_ij(k) / (2 N_k) over the occupied block (the first
+    ``nocc`` orbitals; all by default); their sum over all k is E_x."""
+    n = Kij.shape[1] if nocc is None else nocc
+    return np.real(np.einsum("kii->k", Kij[:, :n, :n])) / (2.0 * nk)
 
 
 def assemble(Kmi, Kij):
@@ -186,12 +196,15 @@ def assemble_projector(Kmi, Kij, S, C):
 
 
 def build(prob, C, chi=None, out_k=None, nyquist="fftfreq", want_k=True, parseval=False, domega=False,
-          kind=None, omega=None, madelung=False):
-    """The whole occ-RI-K build for ``prob`` with coefficients C[k, mu, i].
+          kind=None, omega=None, madelung=False, nvir=0):
+    """The whole occ-RI-K build for ``prob`` with coefficients C[k, mu, p].
 
-    Returns a dict with chi (if computed here), psi, W, Kmi, Kij, ex_terms,
-    Ex (the sum of ex_terms, complete only when out_k covers every k-point), K
-    (assembled, when ``want_k``), and Parseval / d omega sums when requested.
+    The last ``nvir`` columns of C are conduction bands treated exactly (Sec. II.D):
+    the exchange is built from the occupied columns only, K_{mu p} and the block
+    K_pq cover every column, and K~ = K_mu K_pq^-1 K_mu^H.  Returns a dict with chi
+    (if computed here), psi, W, Kmi, Kij, ex_terms, Ex (the sum of ex_terms,
+    complete only when out_k covers every k-point), K (assembled, when ``want_k``),
+    and Parseval / d omega sums when requested.
     """
     geo = Geometry(prob.cell, prob.kmesh, prob.grid, madelung=madelung)
     kind = prob.kernel if kind is None else kind
@@ -199,11 +212,12 @@ def build(prob, C, chi=None, out_k=None, nyquist="fftfreq", want_k=True, parseva
     if chi is None:
         chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
     out_k = list(range(geo.nk)) if out_k is None else list(out_k)
+    nocc = C.shape[2] - nvir
     psi = occupied_orbitals(chi, C)
-    W, ps, pd = exchange_w(geo, psi, out_k, kind, omega, nyquist, parseval, domega)
+    W, ps, pd = exchange_w(geo, psi, out_k, kind, omega, nyquist, parseval, domega, nsum=nocc)
     Kmi = contract(geo, chi[out_k], W)
     Kij = occupied_block(C[out_k], Kmi)
-    terms = exchange_energy_terms(Kij, geo.nk)
+    terms = exchange_energy_terms(Kij, geo.nk, nocc)
     res = dict(chi=chi, psi=psi, W=W, Kmi=Kmi, Kij=Kij, ex_terms=terms, Ex=float(np.sum(terms)), out_k=out_k)
     if want_k:
         res["K"] = assemble(Kmi, Kij)

@@ -591,3 +591,32 @@ def test_madelung_mode_keeps_long_plus_short_range_equal_to_coulomb(small):
     e_lr = occrik.build(prob, C, chi=res["chi"], want_k=False, kind=kernels.ERF_LR, omega=w, madelung=True)["Ex"]
     e_co = occrik.build(prob, C, chi=res["chi"], want_k=False, kind=kernels.COULOMB, madelung=True)["Ex"]
     assert abs(e_sr + e_lr - e_co) < 1e-12 * abs(e_co)
+
+
+# ----------------------------------------------------------------------------
+# Conduction-band extension (Sec. II.D): K~ exact on occupied + selected bands
+# ----------------------------------------------------------------------------
+
+def test_conduction_band_extension_is_exact_on_the_selected_bands():
+    """With nvir extra columns the exchange is still that of the occupied density, and
+    K~ reproduces the conventional exchange on every selected band:
+    K~ C_p = K_conv C_p and C_p^H K~ C_q = C_p^H K_conv C_q for p, q in occ + vir;
+    E_x is the occupied-only one."""
+    nocc, nvir = 2, 2
+    prob = W.small_problem(kmesh=(2, 1, 1), grid=(10, 9, 8), nocc=nocc + nvir, counts=(2, 1, 1))
+    C = W.random_coefficients(prob)                  # nocc + nvir orthonormal columns per k
+    chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+    res = occrik.build(prob, C, chi=chi, nvir=nvir)
+    occ_only = occrik.build(prob, C[:, :, :nocc], chi=chi)
+    Kc = conventional.mo_k(prob, C[:, :, :nocc], chi)
+    assert abs(res["Ex"] - occ_only["Ex"]) < 1e-13 * abs(occ_only["Ex"])
+    KC = np.einsum("kmn,knp->kmp", res["K"], C)
+    KcC = np.einsum("kmn,knp->kmp", Kc, C)
+    assert np.max(np.abs(KC - KcC)) < 1e-11 * np.max(np.abs(KcC))
+    assert np.max(np.abs(res["Kmi"] - KcC)) < 1e-11 * np.max(np.abs(KcC))
+    blk = np.einsum("kmp,kmn,knq->kpq", np.conj(C), res["K"], C)
+    blk_c = np.einsum("kmp,kmn,knq->kpq", np.conj(C), Kc, C)
+    assert np.max(np.abs(blk - blk_c)) < 1e-11 * np.max(np.abs(blk_c))
+    # without the extension the virtual rows of K~ are not the conventional ones
+    KC0 = np.einsum("kmn,knp->kmp", occ_only["K"], C)
+    assert np.max(np.abs(KC0[:, :, nocc:] - KcC[:, :, nocc:])) > 1e-4 * np.max(np.abs(KcC))
