@@ -159,6 +159,12 @@ typedef struct {
     int32_t kbatch;               /* summed k-points per FFT batch; 0 = chosen by the plan */
     int32_t flags;                /* OCCRIK_FLAG_* bits; other bits must be 0 */
     size_t mem_budget;            /* device bytes the plan may allocate; 0 = no limit */
+    int32_t nvir;                 /* conduction bands treated exactly (Sec. II.D), >= 0 with
+                                     nocc + nvir <= 16: C then has nocc + nvir columns per k,
+                                     the last nvir being the bands; the exchange is still built
+                                     from the nocc occupied columns, K_{mu p} and K~ cover all
+                                     columns (K~ C_p equals the conventional K C_p for every
+                                     column), E_x is the occupied trace.  0 = ground state. */
 } occrik_params;
 
 typedef struct occrik_plan occrik_plan;
@@ -175,6 +181,7 @@ typedef struct {
     int32_t integral_direct;      /* 1: chi~ collocated per build (OCCRIK_FLAG_DIRECT) */
     int32_t colloc_chunk;         /* grid points per collocation chunk */
     int32_t reg_fft_passes;       /* bit p-1 set: pair pass p runs register-resident transforms */
+    int32_t nvir;                 /* conduction bands treated exactly */
 } occrik_plan_info;
 
 /* Per-phase device timings of the last build(s), from HIP events recorded on
@@ -214,9 +221,9 @@ occrik_status occrik_set_stream(occrik_plan *plan, void *stream);
 occrik_status occrik_set_omega(occrik_plan *plan, double omega);
 
 /* Synchronous build from host memory.
- *   C   [N_k][N_ao][nocc] complex128 (input)
+ *   C   [N_k][N_ao][nocc + nvir] complex128 (input)
  *   K   [N_k][N_ao][N_ao] complex128 (output K~) or NULL
- *   Kmi [N_k][N_ao][nocc] complex128 (output K_{mu j}) or NULL
+ *   Kmi [N_k][N_ao][nocc + nvir] complex128 (output K_{mu j}) or NULL
  *   Ex  one double (output E_x) or NULL
  * Returns OCCRIK_ERR_NONFINITE for NaN/Inf in C (checked on the host before any
  * device work) and OCCRIK_ERR_NOT_PD when -K_ij(k) has no Cholesky factor. */
@@ -239,7 +246,7 @@ int32_t occrik_last_error_k(const occrik_plan *plan);
 
 /* Gradients of E_x after a build on this plan (not part of the paper; the
  * adjoint of the build).  With gEx = dL/dE_x:
- *   dgradC     [N_k][N_ao][nocc] complex128 device buffer (or NULL) receives
+ *   dgradC     [N_k][N_ao][nocc + nvir] complex128 device buffer (or NULL) receives
  *              gEx * (2/N_k) K_{mu j}, i.e. dL/dRe C + i dL/dIm C.  This is the
  *              exact gradient for OCCRIK_NYQUIST_SYMMETRIC; with FFTFREQ it
  *              differs by a Nyquist-plane term.
@@ -288,8 +295,8 @@ occrik_status occrik_get_profile(occrik_plan *plan, occrik_profile *out, int32_t
 /* Diagnostics: copy a plan-owned intermediate into caller device memory,
  * converted to complex128, row-major.
  *   which = 0: chi~ [N_k][N_ao][N_g], the cell-periodic Bloch AOs e^{-ik.r} chi_{mu k}(r)
- *   which = 1: psi~ [N_k][nocc][N_g], e^{-ik.r} psi_{i k}(r) of the last build
- *   which = 2: W~   [N_k][nocc][N_g], e^{-ik.r} W_{j k}(r) of the last build
+ *   which = 1: psi~ [N_k][nocc + nvir][N_g], e^{-ik.r} psi_{i k}(r) of the last build
+ *   which = 2: W~   [N_k][nocc + nvir][N_g], e^{-ik.r} W_{j k}(r) of the last build
  * bytes must equal the size of that array in complex128. */
 occrik_status occrik_copy_intermediate(occrik_plan *plan, int32_t which, void *dst, size_t bytes);
 

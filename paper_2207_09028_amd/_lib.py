@@ -45,7 +45,7 @@ class Basis(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("kmesh", c_int32 * 3), ("grid", c_int32 * 3), ("nocc", c_int32), ("kernel", c_int32),
                 ("omega", c_double), ("nyquist", c_int32), ("precision", c_int32), ("lattice_tol", c_double),
-                ("kbatch", c_int32), ("flags", c_int32), ("mem_budget", c_size_t)]
+                ("kbatch", c_int32), ("flags", c_int32), ("mem_budget", c_size_t), ("nvir", c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
                 ("omega", c_double), ("cell_volume", c_double),
                 ("bytes_chi", c_size_t), ("bytes_workspace", c_size_t),
                 ("pair_transforms", ctypes.c_int64), ("plan_seconds", c_double),
-                ("integral_direct", c_int32), ("colloc_chunk", c_int32), ("reg_fft_passes", c_int32)]
+                ("integral_direct", c_int32), ("colloc_chunk", c_int32), ("reg_fft_passes", c_int32),
+                ("nvir", c_int32)]
 
 
 class Profile(ctypes.Structure):

@@ -39,7 +39,8 @@ __global__ void reset_flags_kernel(int* flags, int n) {
 
 __global__ void __launch_bounds__(256) kij_kernel(const double2* __restrict__ C, const double2* __restrict__ Kmi,
                                                   double2* __restrict__ Kij, double2* __restrict__ L,
-                                                  double* __restrict__ eterm, int* flags, int nk, int nao, int nocc) {
+                                                  double* __restrict__ eterm, int* flags, int nk, int nao, int nocc,
+                                                  int nocc_e) {
     __shared__ double2 kij[kMaxOccA * kMaxOccA];
     __shared__ double2 l[kMaxOccA * kMaxOccA];
     const int k = blockIdx.x;
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(256) kij_kernel(const double2* __restrict__ C,
     if (t == 0) {
         const int n = nocc;
         double tr = 0.0;
-        for (int i = 0; i < n; ++i) tr += kij[i * n + i].x;
+        for (int i = 0; i < nocc_e; ++i) tr += kij[i * n + i].x;      // occupied orbitals only
         eterm[k] = tr / (2.0 * nk);
         bool ok = true;
         for (int i = 0; i < n * n; ++i) l[i] = make_double2(0.0, 0.0);
@@ -163,6 +164,15 @@ __global__ void sum_f64_kernel(const double* __restrict__ parts, size_t n, doubl
     if (threadIdx.x == 0) *out += scale * red[0];
 }
 
+__global__ void grad_columns_kernel(const double2* __restrict__ src, double2* __restrict__ dst, size_t rows,
+                                    int ncol, int nkeep, double scale) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * ncol) return;
+    const int c = (int)(t % ncol);
+    const double2 v = src[t];
+    dst[t] = c < nkeep ? make_double2(scale * v.x, scale * v.y) : make_double2(0.0, 0.0);
+}
+
 __global__ void scale_copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, size_t n, double scale) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = make_double2(scale * src[i].x, scale * src[i].y);
@@ -191,8 +201,9 @@ hipError_t launch_reset_flags_n(int* flags, int n, hipStream_t s) {
 }
 
 hipError_t launch_kij(const double2* C, const double2* Kmi, double2* Kij, double2* L, double* eterm, int* flags,
-                      int nk, int nao, int nocc, hipStream_t s) {
-    hipLaunchKernelGGL(kij_kernel, dim3((unsigned)nk), dim3(256), 0, s, C, Kmi, Kij, L, eterm, flags, nk, nao, nocc);
+                      int nk, int nao, int ncol, int nocc, hipStream_t s) {
+    hipLaunchKernelGGL(kij_kernel, dim3((unsigned)nk), dim3(256), 0, s, C, Kmi, Kij, L, eterm, flags, nk, nao, ncol,
+                       nocc);
     return hipGetLastError();
 }
 
@@ -216,6 +227,15 @@ hipError_t launch_energy(const double* eterm, int nk, double* out, hipStream_t s
 
 hipError_t launch_sum_f64(const double* parts, size_t n, double scale, double* out, hipStream_t s) {
     hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(256), 0, s, parts, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_columns(const double2* src, double2* dst, size_t rows, int ncol, int nkeep, double scale,
+                               hipStream_t s) {
+    const size_t n = rows * ncol;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_columns_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, rows, ncol,
+                       nkeep, scale);
     return hipGetLastError();
 }
 

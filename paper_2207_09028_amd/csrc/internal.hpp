@@ -14,15 +14,18 @@
 namespace occrik {
 
 // One batch of pair round trips: output k-point a, blocks (a, b) for b in
-// [b0, b0 + nb).  Stored pairs ("slots"): block b holds the nocc x nocc pairs
-// (i at b, j at a) at slot base + i * nocc + j; with conjugate-pair reuse the
+// [b0, b0 + nb).  Stored pairs ("slots"): block b holds the nocc x nout pairs
+// (i at b summed, j at a output) at slot base + i * nout + j; with conjugate-pair
+// reuse (square pair sets only, nout == nocc) the
 // batch starts at b0 >= a and, when b0 == a, the diagonal block comes first and
 // holds only the pairs i <= j (nocc (nocc + 1) / 2 slots, upper-triangle rows).
 // The density of a slot is conj(psi~_{i b}) psi~_{j a}, momentum q = k_a - k_b.
 struct PairBatch {
     int N1, N2, N3, ng;
     int M1, M2, M3;
-    int nocc;
+    int nocc;                 // summed (occupied) orbitals per k: pair index i
+    int nout;                 // output orbitals of the pairs: index j (nocc + conduction bands)
+    int kstride;              // orbitals per k in the psi~ and W~ arrays
     int a, b0, nb;
     int reuse;                // conjugate-pair reuse (symmetric Nyquist mode)
     int diag;                 // the first block is the diagonal block (a, a)
@@ -94,14 +97,19 @@ hipError_t launch_contract_reduce(const double2* Kpart, double2* Kmi, size_t n, 
 
 hipError_t launch_check_finite(const double2* C, size_t n, int* flags, hipStream_t s);
 hipError_t launch_reset_flags_n(int* flags, int n, hipStream_t s);
+// K_pq = C^H K_{mu q} (ncol x ncol per k), its Cholesky factor, and the energy term
+// Re tr over the first nocc (occupied) orbitals / (2 N_k)
 hipError_t launch_kij(const double2* C, const double2* Kmi, double2* Kij, double2* L, double* eterm, int* flags,
-                      int nk, int nao, int nocc, hipStream_t s);
+                      int nk, int nao, int ncol, int nocc, hipStream_t s);
 hipError_t launch_xi(const double2* Kmi, const double2* L, double2* Y, const int* flags, int nk, int nao, int nocc,
                      hipStream_t s);
 hipError_t launch_ktilde(const double2* Y, double2* K, const int* flags, int nk, int nao, int nocc, hipStream_t s);
 hipError_t launch_energy(const double* eterm, int nk, double* out, hipStream_t s);
 hipError_t launch_sum_f64(const double* parts, size_t n, double scale, double* out, hipStream_t s);
 hipError_t launch_scale_copy(const double2* src, double2* dst, size_t n, double scale, hipStream_t s);
+// dst[r][c] = scale * src[r][c] for c < nkeep, 0 for nkeep <= c < ncol
+hipError_t launch_grad_columns(const double2* src, double2* dst, size_t rows, int ncol, int nkeep, double scale,
+                               hipStream_t s);
 
 // Collocation: at plan time into the stored chi~, or per build and per grid chunk in
 // integral-direct plans; both run the same per-point arithmetic.

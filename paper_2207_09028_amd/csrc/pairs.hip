@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
     int b, i, j;
     decode_slot(B, slot, b, i, j);
     load_twiddles<T>(tw, twg);
-    const cplx<T>* pj = psi + ((size_t)B.a * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
-    const cplx<T>* pi = psi + ((size_t)b * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+    const cplx<T>* pj = psi + ((size_t)B.a * B.kstride + j) * B.ng + (size_t)n1 * plane_sz;
+    const cplx<T>* pi = psi + ((size_t)b * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
     constexpr int PTS = ((NN > 0 ? NN * NN : kMaxN * kMaxN) + kFftThreads - 1) / kFftThreads;
 #pragma unroll
     for (int t = 0; t < PTS; ++t) {
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     const int grp = blockIdx.x / N2;
     // group -> (block, first slot, slot count); the diagonal block (if any) comes first
     const int P = B.group;
-    const int nn = B.nocc * B.nocc;
+    const int nn = B.nocc * B.nout;
     const int gd = B.diag ? (B.ntri + P - 1) / P : 0;
     const int go = (nn + P - 1) / P;
     int s0, s1, b;
@@ -252,8 +252,8 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
     const Dims<NN> D(B);
     const int N2 = D.n2, N3 = D.n3, S = N3 + 1;
     const int plane_sz = N2 * N3;
-    const int nA = D.n1 * B.nocc * B.splits;
-    const int nn = B.nocc * B.nocc;
+    const int nA = D.n1 * B.nout * B.splits;
+    const int nn = B.nocc * B.nout;
     const int first_full = B.b0 + (B.diag ? 1 : 0);
     const int full_base = B.diag ? B.ntri : 0;
     load_twiddles<T>(tw, twg);
@@ -288,8 +288,8 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
     if ((int)blockIdx.x < nA) {
         // a-side: W~_{j a}(plane n1) partial over a slice of the (b, i) sum
         const int n1 = blockIdx.x % D.n1;
-        const int j = (blockIdx.x / D.n1) % B.nocc;
-        const int s = blockIdx.x / (D.n1 * B.nocc);
+        const int j = (blockIdx.x / D.n1) % B.nout;
+        const int s = blockIdx.x / (D.n1 * B.nout);
         const int total = B.nb * B.nocc;
         const int chunk = (total + B.splits - 1) / B.splits;
         const int q0 = s * chunk;
@@ -305,12 +305,12 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
                     cj = true;
                 }
             } else {
-                slot = full_base + (bb - first_full) * nn + i * B.nocc + j;
+                slot = full_base + (bb - first_full) * nn + i * B.nout + j;
             }
-            const cplx<T>* pi = psi + ((size_t)bb * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+            const cplx<T>* pi = psi + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
             term(slot, cj, pi, n1);
         }
-        cplx<T>* out = Wpart + ((size_t)s * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
+        cplx<T>* out = Wpart + ((size_t)s * B.nout + j) * B.ng + (size_t)n1 * plane_sz;
 #pragma unroll
         for (int t = 0; t < ACC; ++t) {
             const int e = threadIdx.x + t * kFftThreads;
@@ -324,11 +324,11 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
         const int blk = g / (D.n1 * B.nocc);
         const int bb = first_full + blk;
         for (int j = 0; j < B.nocc; ++j) {
-            const int slot = full_base + blk * nn + i * B.nocc + j;
-            const cplx<T>* pj = psi + ((size_t)B.a * B.nocc + j) * B.ng + (size_t)n1 * plane_sz;
+            const int slot = full_base + blk * nn + i * B.nout + j;
+            const cplx<T>* pj = psi + ((size_t)B.a * B.kstride + j) * B.ng + (size_t)n1 * plane_sz;
             term(slot, true, pj, n1);
         }
-        cplx<T>* out = W + ((size_t)bb * B.nocc + i) * B.ng + (size_t)n1 * plane_sz;
+        cplx<T>* out = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
 #pragma unroll
         for (int t = 0; t < ACC; ++t) {
             const int e = threadIdx.x + t * kFftThreads;
@@ -385,8 +385,8 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     const int cb = (blockIdx.x / NN) % NCB;
     const int s = blockIdx.x / (NN * NCB);
     const int c0 = cb * WB;
-    const int nocc = B.nocc;
-    const int nn = nocc * nocc;
+    const int nocc = B.nocc, nout = B.nout;
+    const int nn = nocc * nout;
     const int total = B.nb * nocc;
     const int chunk = (total + B.splits - 1) / B.splits;
     const int q0 = s * chunk;
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     const int r0 = threadIdx.x / LNP;
     const int jl = lane / WB;
     const int w = lane - jl * WB;
-    const bool active = lane < LN && jl < nocc;
+    const bool active = lane < LN && jl < nout;
     load_twiddles<T>(tw, twg);
     const size_t plane_off = (size_t)n1 * PLANE + c0 + w;
     // stored slot of (b, i; jl, a) for summed pair q = (b - b0) nocc + i, and whether it
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
             cj = jl < i;
             return cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
         }
-        return full_base + (bb - first_full) * nn + i * nocc + jl;
+        return full_base + (bb - first_full) * nn + i * nout + jl;
     };
     auto load_column = [&](int q, cplx<T>* dst) {
         bool cj;
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     // spill): the next pair's column is loaded while this pair is transformed, and the
     // a-side orbital at this thread's points, the same for every summed pair, is held.
     constexpr bool PF = JC <= 8;
-    const cplx<T>* pa_src = psi + ((size_t)B.a * nocc + (active ? jl : 0)) * B.ng + plane_off;
+    const cplx<T>* pa_src = psi + ((size_t)B.a * B.kstride + (active ? jl : 0)) * B.ng + plane_off;
     cplx<T> pa[PT];
     if constexpr (PF) {
 #pragma unroll
@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
         // in flight during this pair's transform: the next pair's column, this pair's
         // b-side orbital values and its W block
         if (PF && q + 1 < q1) load_column(q + 1, xn);
-        const cplx<T>* ui_src = psi + ((size_t)bb * nocc + i) * B.ng + plane_off;
+        const cplx<T>* ui_src = psi + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
         cplx<T> ui[PT];
         if constexpr (PF) {
 #pragma unroll
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
                 ui[t] = (active && n2 < NN) ? ui_src[(size_t)n2 * NN] : mk<T>(T(0), T(0));
             }
         }
-        cplx<T>* wout = W + ((size_t)bb * nocc + i) * B.ng + (size_t)n1 * PLANE + c0;
+        cplx<T>* wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
         cplx<T> wv[BPT];
         if (PF && bside) {
 #pragma unroll
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
         }
     }
     if (active) {
-        cplx<T>* out = Wpart + ((size_t)s * nocc + jl) * B.ng + plane_off;
+        cplx<T>* out = Wpart + ((size_t)s * nout + jl) * B.ng + plane_off;
 #pragma unroll
         for (int t = 0; t < PT; ++t) {
             const int n2 = r0 + t * RPI;
@@ -518,11 +518,12 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
 template <typename T>
 __global__ void wreduce_kernel(PairBatch B, const cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W) {
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t tot = (size_t)B.nocc * B.ng;
+    const size_t tot = (size_t)B.nout * B.ng;               // partials: [split][nout][ng]
     if (n >= tot) return;
-    cplx<T> acc = W[(size_t)B.a * tot + n];
+    cplx<T>* w = W + (size_t)B.a * B.kstride * B.ng;        // the output orbitals at k_a
+    cplx<T> acc = w[n];
     for (int s = 0; s < B.splits; ++s) acc = cadd<T>(acc, Wpart[(size_t)s * tot + n]);
-    W[(size_t)B.a * tot + n] = acc;
+    w[n] = acc;
 }
 
 template <typename T>
@@ -566,7 +567,7 @@ inline int specialised(const PairBatch& B) {
 }  // namespace
 
 int pair_groups(const PairBatch& B) {
-    const int nn = B.nocc * B.nocc;
+    const int nn = B.nocc * B.nout;
     const int gd = B.diag ? (B.ntri + B.group - 1) / B.group : 0;
     const int nfull = B.nb - (B.diag ? 1 : 0);
     return gd + nfull * ((nn + B.group - 1) / B.group);
@@ -606,7 +607,7 @@ hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, doubl
 int pass3_splits(const PairBatch& B, int elem) {
     const int target_wg = 2048;
     const int nn = specialised(B);
-    const int base_wg = nn > 0 && B.nocc <= 16 ? nn * (nn / colblock(nn, elem)) : B.N1 * B.nocc;
+    const int base_wg = nn > 0 && B.nout <= 16 ? nn * (nn / colblock(nn, elem)) : B.N1 * B.nout;
     return std::max(1, std::min(B.nb * B.nocc, (target_wg + base_wg - 1) / base_wg));
 }
 
@@ -614,12 +615,12 @@ template <typename T>
 hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi, cplx<T>* Wpart, cplx<T>* W,
                         const cplx<T>* tw, hipStream_t s) {
     if constexpr (std::is_same_v<T, float>)
-        if ((B.regfft & REGFFT_PASS3) && B.nocc <= 8) return launch_pass3_reg(B, X, psi, Wpart, W, s);
+        if ((B.regfft & REGFFT_PASS3) && B.nout <= 8) return launch_pass3_reg(B, X, psi, Wpart, W, s);
     const int nnv = specialised(B);
-    if (nnv > 0 && B.nocc <= 16) {
+    if (nnv > 0 && B.nout <= 16) {
         const int wb = colblock(nnv, (int)sizeof(cplx<T>));
         const unsigned grid = (unsigned)((size_t)nnv * (nnv / wb) * B.splits);
-        const int jc = B.nocc <= 8 ? 8 : 16;
+        const int jc = B.nout <= 8 ? 8 : 16;
         int lnp = 1;
         while (lnp < jc * wb) lnp *= 2;
         const size_t lds = sizeof(cplx<T>) * (3 * kMaxN + (size_t)nnv * lnp);
@@ -635,7 +636,7 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
         return hipGetLastError();
     }
     const int nfull_b = B.reuse ? B.nb - (B.diag ? 1 : 0) : 0;
-    const unsigned grid = (unsigned)((size_t)B.N1 * B.nocc * B.splits + (size_t)nfull_b * B.nocc * B.N1);
+    const unsigned grid = (unsigned)((size_t)B.N1 * B.nout * B.splits + (size_t)nfull_b * B.nocc * B.N1);
     const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
     hipLaunchKernelGGL((pass3_kernel<T, 0>), dim3(grid), dim3(kFftThreads), lds, s, B, X, psi, Wpart, W, tw);
     return hipGetLastError();
@@ -643,7 +644,7 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
 
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s) {
-    const size_t tot = (size_t)B.nocc * B.ng;
+    const size_t tot = (size_t)B.nout * B.ng;
     hipLaunchKernelGGL(wreduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, Wpart, W);
     return hipGetLastError();
 }

@@ -152,7 +152,7 @@ __device__ inline int tri_index(int i, int j, int nocc) { return i * nocc - (i *
 
 // Stored pair slot -> (b, i, j).
 __device__ inline void decode_slot(const PairBatch& B, int slot, int& b, int& i, int& j) {
-    const int nn = B.nocc * B.nocc;
+    const int nn = B.nocc * B.nout;
     if (B.diag && slot < B.ntri) {
         int r = 0;
         while (r + 1 < B.nocc && tri_index(r + 1, r + 1, B.nocc) <= slot) ++r;
@@ -165,8 +165,8 @@ __device__ inline void decode_slot(const PairBatch& B, int slot, int& b, int& i,
     const int blk = s / nn;
     const int rem = s - blk * nn;
     b = B.b0 + (B.diag ? 1 : 0) + blk;
-    i = rem / B.nocc;
-    j = rem - i * B.nocc;
+    i = rem / B.nout;
+    j = rem - i * B.nout;
 }
 
 

@@ -72,6 +72,7 @@ struct occrik_plan {
     double lat[9]{}, recip[9]{}, volume = 0.0, dv = 0.0;
     int N[3]{}, M[3]{};
     int nk = 0, ng = 0, nao = 0, nocc = 0, natm = 0;
+    int nvir = 0, nout = 0;     // conduction bands treated exactly; nout = nocc + nvir columns of C
     std::vector<double> atom_cart;
     std::vector<int> shell_atom, shell_l;
     std::vector<double> shell_exp;
@@ -84,10 +85,10 @@ struct occrik_plan {
     std::vector<size_t> sizes;
     size_t bytes_alloc = 0, bytes_chi = 0;
     void* chi = nullptr;       // [nk][nao][ng] cplx<T>
-    void* psi = nullptr;       // [nk][nocc][ng]
-    void* W = nullptr;         // [nk][nocc][ng]
-    void* X = nullptr;         // [kbatch * nocc^2][ng]
-    void* Wpart = nullptr;     // [splits][nocc][ng]
+    void* psi = nullptr;       // [nk][nout][ng]
+    void* W = nullptr;         // [nk][nout][ng]
+    void* X = nullptr;         // [kbatch * nocc * nout][ng]
+    void* Wpart = nullptr;     // [splits][nout][ng]
     void* tw = nullptr;        // [3][kMaxN]
     double* parts = nullptr;   // [kbatch * nocc^2 * N2]
     void* kvals = nullptr;     // [kbatch][ng] kernel values of a batch, working precision
@@ -104,11 +105,11 @@ struct occrik_plan {
     double madelung_g0 = 0.0;  // Madelung mode: N_k Omega M_s of the k-mesh supercell (0: off)
     void* chi_ws = nullptr;    // direct: [nk][nao][cchunk] chi~ of one chunk
     bool regfft = false;       // complex64 pair passes with register-resident transforms
-    double2* Kpart = nullptr;  // [nk][nao][nocc][nchunks]
-    double2* Kmi = nullptr;    // [nk][nao][nocc]
-    double2* Kij = nullptr;    // [nk][nocc][nocc]
-    double2* L = nullptr;      // [nk][nocc][nocc]
-    double2* Y = nullptr;      // [nk][nao][nocc]
+    double2* Kpart = nullptr;  // [nk][nao][nout][nchunks]
+    double2* Kmi = nullptr;    // [nk][nao][nout]
+    double2* Kij = nullptr;    // [nk][nout][nout]
+    double2* L = nullptr;      // [nk][nout][nout]
+    double2* Y = nullptr;      // [nk][nao][nout]
     double* eterm = nullptr;   // [nk]
     double* scal = nullptr;    // [4] device scalars
     int* flags = nullptr;      // [2 + nk]
@@ -420,7 +421,11 @@ occrik_status make_twiddles(occrik_plan* P) {
     return OCCRIK_OK;
 }
 
-bool plan_reuses_pairs(const occrik_plan* P) { return P->params.nyquist == OCCRIK_NYQUIST_SYMMETRIC; }
+// conjugate-pair reuse needs exact conjugate pairs (symmetric Nyquist mode) and a square
+// pair set: with conduction bands the mirror of an (occupied, virtual) pair is not summed
+bool plan_reuses_pairs(const occrik_plan* P) {
+    return P->params.nyquist == OCCRIK_NYQUIST_SYMMETRIC && P->nvir == 0;
+}
 
 int splits_for(const occrik_plan* P, int nb) {
     PairBatch B{};
@@ -428,11 +433,13 @@ int splits_for(const occrik_plan* P, int nb) {
     B.N2 = P->N[1];
     B.N3 = P->N[2];
     B.nocc = P->nocc;
+    B.nout = P->nout;
     B.nb = nb;
     return pass3_splits(B, (int)P->elem);
 }
 
-PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
+// occ_only: pairs with occupied output orbitals only (the energy-derivative sweep)
+PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb, bool occ_only = false) {
     PairBatch B{};
     B.N1 = P->N[0];
     B.N2 = P->N[1];
@@ -442,13 +449,15 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
     B.M2 = P->M[1];
     B.M3 = P->M[2];
     B.nocc = P->nocc;
+    B.nout = occ_only ? P->nocc : P->nout;
+    B.kstride = P->nout;
     B.a = a;
     B.b0 = b0;
     B.nb = nb;
     B.reuse = plan_reuses_pairs(P) ? 1 : 0;
     B.diag = (B.reuse && b0 == a) ? 1 : 0;
     B.ntri = P->nocc * (P->nocc + 1) / 2;
-    const int nn = P->nocc * P->nocc;
+    const int nn = B.nocc * B.nout;
     B.nslots = B.diag ? B.ntri + (nb - 1) * nn : nb * nn;
     B.group = P->group;
     B.kernel = P->params.kernel;
@@ -471,7 +480,7 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb) {
 template <typename T>
 occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2* dKmi, double* dEx) {
     hipStream_t s = P->stream;
-    const int nk = P->nk, nao = P->nao, nocc = P->nocc, ng = P->ng;
+    const int nk = P->nk, nao = P->nao, nocc = P->nout, ng = P->ng;   // nocc here: columns of C
     cplx<T>* chi = reinterpret_cast<cplx<T>*>(P->chi);
     cplx<T>* psi = reinterpret_cast<cplx<T>*>(P->psi);
     cplx<T>* W = reinterpret_cast<cplx<T>*>(P->W);
@@ -548,7 +557,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[3], s));
     // a copy kernel rather than a memcpy, so that a captured build holds kernel nodes only
     if (dKmi) OCCRIK_HIP(launch_scale_copy(P->Kmi, (double2*)dKmi, (size_t)nk * nao * nocc, 1.0, s));
-    OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, s));
+    OCCRIK_HIP(launch_kij(dC, P->Kmi, P->Kij, P->L, P->eterm, P->flags, nk, nao, nocc, P->nocc, s));
     if (dK) {
         OCCRIK_HIP(launch_xi(P->Kmi, P->L, P->Y, P->flags, nk, nao, nocc, s));
         OCCRIK_HIP(launch_ktilde(P->Y, dK, P->flags, nk, nao, nocc, s));
@@ -576,7 +585,7 @@ occrik_status domega_impl(occrik_plan* P, double* out_host) {
     for (int a = 0; a < nk; ++a)
         for (int b0 = reuse ? a : 0; b0 < nk; b0 += P->kbatch) {
             const int nb = std::min(P->kbatch, nk - b0);
-            PairBatch B = make_batch(P, a, b0, nb);
+            PairBatch B = make_batch(P, a, b0, nb, true);
             OCCRIK_HIP(launch_pass1<T>(B, psi, X, tw, s));
             OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 1, s));
             OCCRIK_HIP(launch_sum_f64(P->parts, (size_t)pair_groups(B) * P->N[1], scale, P->scal, s));
@@ -612,6 +621,8 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
             return fail(OCCRIK_ERR_UNSUPPORTED, "grid size " + std::to_string(pr->grid[d]) + " not supported");
     }
     if (pr->nocc < 1 || pr->nocc > 16) return fail(OCCRIK_ERR_INVALID_ARG, "nocc must be 1..16");
+    if (pr->nvir < 0 || pr->nocc + pr->nvir > 16)
+        return fail(OCCRIK_ERR_INVALID_ARG, "nvir must be >= 0 with nocc + nvir <= 16");
     if (pr->kernel < 0 || pr->kernel > 4) return fail(OCCRIK_ERR_INVALID_ARG, "unknown kernel");
     const bool range_separated = pr->kernel == OCCRIK_KERNEL_ERF_LR || pr->kernel == OCCRIK_KERNEL_ERFC_SR ||
                                  pr->kernel == OCCRIK_KERNEL_TRUNC_ERF_LR;
@@ -708,17 +719,19 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         P->maxcomp = std::max(P->maxcomp, (l + 1) * (l + 2) / 2);
     }
     P->nocc = params->nocc;
-    if (P->nocc > P->nao) {
+    P->nvir = params->nvir;
+    P->nout = P->nocc + P->nvir;
+    if (P->nout > P->nao) {
         delete P;
-        return fail(OCCRIK_ERR_INVALID_ARG, "nocc exceeds the number of AOs");
+        return fail(OCCRIK_ERR_INVALID_ARG, "nocc + nvir exceeds the number of AOs");
     }
     P->fp64 = params->precision == OCCRIK_PREC_FP64;
     P->elem = P->fp64 ? 16 : 8;
-    P->regfft = !P->fp64 && !(params->flags & OCCRIK_FLAG_LDS_FFT) &&
+    P->regfft = !P->fp64 && !(params->flags & OCCRIK_FLAG_LDS_FFT) && params->nvir == 0 &&
                 reg_fft_size(params->grid[0], params->grid[1], params->grid[2]);
 
-    const int nk = P->nk, ng = P->ng, nao = P->nao, nocc = P->nocc;
-    const size_t per_k = (size_t)nocc * nocc * ng * P->elem;
+    const int nk = P->nk, ng = P->ng, nao = P->nao, nocc = P->nocc, nout = P->nout;
+    const size_t per_k = (size_t)nocc * nout * ng * P->elem;
     if (params->kbatch > 0) {
         P->kbatch = std::min(params->kbatch, nk);
     } else {
@@ -726,9 +739,9 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         P->kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_k));
     }
     P->splits = splits_for(P, P->kbatch);
-    P->group = nocc;
+    P->group = nout;
     P->nchunks = std::max(1, std::min(64, ng / 4096));
-    const size_t max_groups = (size_t)P->kbatch * ((nocc * nocc + P->group - 1) / P->group) +
+    const size_t max_groups = (size_t)P->kbatch * ((nocc * nout + P->group - 1) / P->group) +
                               (nocc * (nocc + 1) / 2 + P->group - 1) / P->group;
 
     hipError_t e = hipSuccess;
@@ -750,8 +763,8 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     // would not fit next to the other workspaces: within mem_budget when one is
     // set, else within the device memory free now.
     const size_t bytes_chi_stored = (size_t)nk * nao * ng * P->elem;
-    const size_t bytes_other = (size_t)nk * nocc * ng * P->elem * 2 + (size_t)P->kbatch * per_k +
-                               (size_t)P->splits * nocc * ng * P->elem + sizeof(double2) * (size_t)nk * nao * nocc *
+    const size_t bytes_other = (size_t)nk * nout * ng * P->elem * 2 + (size_t)P->kbatch * per_k +
+                               (size_t)P->splits * nout * ng * P->elem + sizeof(double2) * (size_t)nk * nao * nout *
                                (P->nchunks + 2) + P->elem / 2 * (size_t)P->kbatch * ng;
     const size_t bytes_scratch = (sizeof(double) * P->maxcomp + 2 * sizeof(double2)) * (size_t)nk * P->cchunk;
     P->direct = (params->flags & OCCRIK_FLAG_DIRECT) != 0;
@@ -770,18 +783,18 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         P->bytes_chi = bytes_chi_stored;
         A(&P->chi, P->bytes_chi);
     }
-    A(&P->psi, (size_t)nk * nocc * ng * P->elem);
-    A(&P->W, (size_t)nk * nocc * ng * P->elem);
+    A(&P->psi, (size_t)nk * nout * ng * P->elem);
+    A(&P->W, (size_t)nk * nout * ng * P->elem);
     A(&P->X, (size_t)P->kbatch * per_k);
-    A(&P->Wpart, (size_t)P->splits * nocc * ng * P->elem);
+    A(&P->Wpart, (size_t)P->splits * nout * ng * P->elem);
     A(&P->tw, 3 * kMaxN * P->elem);
     A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
     A(&P->kvals, P->elem / 2 * (size_t)P->kbatch * ng);
-    A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nocc * P->nchunks);
-    A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nocc);
-    A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nocc * nocc);
-    A((void**)&P->L, sizeof(double2) * (size_t)nk * nocc * nocc);
-    A((void**)&P->Y, sizeof(double2) * (size_t)nk * nao * nocc);
+    A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nout * P->nchunks);
+    A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nout);
+    A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nout * nout);
+    A((void**)&P->L, sizeof(double2) * (size_t)nk * nout * nout);
+    A((void**)&P->Y, sizeof(double2) * (size_t)nk * nao * nout);
     A((void**)&P->eterm, sizeof(double) * nk);
     A((void**)&P->scal, sizeof(double) * 4);
     A((void**)&P->flags, sizeof(int) * (2 + nk));
@@ -821,6 +834,7 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
     info->nk = P->nk;
     info->nao = P->nao;
     info->nocc = P->nocc;
+    info->nvir = P->nvir;
     info->ng = P->ng;
     for (int d = 0; d < 3; ++d) {
         info->grid[d] = P->N[d];
@@ -835,12 +849,12 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
     info->bytes_chi = P->bytes_chi;
     info->integral_direct = P->direct ? 1 : 0;
     info->colloc_chunk = P->cchunk;
-    info->reg_fft_passes = make_batch(P, 0, 0, 1).regfft & (P->nocc <= 8 ? ~0 : ~REGFFT_PASS3);
+    info->reg_fft_passes = make_batch(P, 0, 0, 1).regfft & (P->nout <= 8 ? ~0 : ~REGFFT_PASS3);
     info->bytes_workspace = P->bytes_alloc - P->bytes_chi;
     info->pair_transforms = plan_reuses_pairs(P)
                                 ? (int64_t)P->nk * (P->nk - 1) / 2 * P->nocc * P->nocc +
                                       (int64_t)P->nk * P->nocc * (P->nocc + 1) / 2
-                                : (int64_t)P->nk * P->nk * P->nocc * P->nocc;
+                                : (int64_t)P->nk * P->nk * P->nocc * P->nout;
     info->plan_seconds = P->plan_seconds;
     return OCCRIK_OK;
 }
@@ -886,7 +900,7 @@ int32_t occrik_last_error_k(const occrik_plan* P) { return P ? P->last_err_k : -
 occrik_status occrik_build(occrik_plan* P, const double* C, double* K, double* Kmi, double* Ex) {
     if (!P || !C) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C");
     DeviceGuard guard(P->device);
-    const size_t nC = (size_t)P->nk * P->nao * P->nocc * 2;
+    const size_t nC = (size_t)P->nk * P->nao * P->nout * 2;
     for (size_t i = 0; i < nC; ++i)
         if (!std::isfinite(C[i])) return fail(OCCRIK_ERR_NONFINITE, "non-finite entries in C");
     const size_t bC = nC * sizeof(double);
@@ -922,8 +936,10 @@ occrik_status occrik_grad(occrik_plan* P, double gEx, void* dgradC, double* dgra
     if (!std::isfinite(gEx)) return fail(OCCRIK_ERR_INVALID_ARG, "non-finite gEx");
     DeviceGuard guard(P->device);
     if (dgradC)
-        OCCRIK_HIP(launch_scale_copy(P->Kmi, (double2*)dgradC, (size_t)P->nk * P->nao * P->nocc, gEx * 2.0 / P->nk,
-                                     P->stream));
+        // dE_x/dC = (2 / N_k) K_{mu j} on the occupied columns; E_x does not depend on the
+        // conduction-band columns, whose gradient is zero
+        OCCRIK_HIP(launch_grad_columns(P->Kmi, (double2*)dgradC, (size_t)P->nk * P->nao, P->nout, P->nocc,
+                                       gEx * 2.0 / P->nk, P->stream));
     if (dgradOmega) {
         double d = 0.0;
         if (P->params.kernel != OCCRIK_KERNEL_COULOMB) {
@@ -980,8 +996,8 @@ double build_cost(const occrik_plan* P) {
     const double pairs = plan_reuses_pairs(P)
                              ? double(P->nk) * (P->nk - 1) / 2 * P->nocc * P->nocc +
                                    double(P->nk) * P->nocc * (P->nocc + 1) / 2
-                             : double(P->nk) * P->nk * P->nocc * P->nocc;
-    return pairs * P->ng * std::log2(double(P->ng)) + 2.0 * P->nk * P->nao * P->nocc * double(P->ng);
+                             : double(P->nk) * P->nk * P->nocc * P->nout;
+    return pairs * P->ng * std::log2(double(P->ng)) + 2.0 * P->nk * P->nao * P->nout * double(P->ng);
 }
 
 occrik_status validate_batch(int32_t n, occrik_plan* const* plans, const void* const* dC) {
@@ -1155,7 +1171,7 @@ occrik_status occrik_copy_intermediate(occrik_plan* P, int32_t which, void* dst,
     } else if (which == 1 || which == 2) {
         if (!P->built) return fail(OCCRIK_ERR_STATE, "no build yet");
         src = which == 1 ? P->psi : P->W;
-        n = (size_t)P->nk * P->nocc * P->ng;
+        n = (size_t)P->nk * P->nout * P->ng;
     } else {
         return fail(OCCRIK_ERR_INVALID_ARG, "which must be 0, 1 or 2");
     }

@@ -3,9 +3,9 @@
 PyTorch supplies device memory and the current HIP stream; every step of a
 build runs in the library's HIP kernels.  Arrays follow the C layouts:
 
-    C    [N_k, N_ao, nocc]  complex128  occupied coefficients
+    C    [N_k, N_ao, nocc + nvir]  complex128  occupied coefficients, then nvir conduction bands
     K    [N_k, N_ao, N_ao]  complex128  assembled exchange matrix K~
-    Kmi  [N_k, N_ao, nocc]  complex128  K_{mu j}
+    Kmi  [N_k, N_ao, nocc + nvir]  complex128  K_{mu j}
     Ex   scalar float64                  exchange energy per cell and spin
 """
 from __future__ import annotations
@@ -42,6 +42,7 @@ class PlanSpec:
     kbatch: int = 0
     mem_budget: int = 0
     flags: int = 0
+    nvir: int = 0
 
     @classmethod
     def from_problem(cls, prob, **overrides):
@@ -78,7 +79,8 @@ class Plan:
                            self._se.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         params = _lib.Params((ctypes.c_int32 * 3)(*spec.kmesh), (ctypes.c_int32 * 3)(*spec.grid), int(spec.nocc),
                              int(spec.kernel), float(spec.omega), int(spec.nyquist), int(spec.precision),
-                             float(spec.lattice_tol), int(spec.kbatch), int(spec.flags), int(spec.mem_budget))
+                             float(spec.lattice_tol), int(spec.kbatch), int(spec.flags), int(spec.mem_budget),
+                             int(spec.nvir))
         handle = _lib.PlanP()
         with torch.cuda.device(self.device):
             st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params),
@@ -88,6 +90,8 @@ class Plan:
         self._lib = lib
         self.info = self.query()
         self.nk, self.nao, self.nocc, self.ng = self.info.nk, self.info.nao, self.info.nocc, self.info.ng
+        self.nvir = self.info.nvir
+        self.ncol = self.nocc + self.nvir        # columns of C, K_{mu j}, psi~ and W~
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -123,13 +127,13 @@ class Plan:
     def _check_C(self, C):
         if not isinstance(C, torch.Tensor) or C.dtype != torch.complex128 or C.device != self.device:
             raise TypeError("C must be a complex128 tensor on the plan's device")
-        if tuple(C.shape) != (self.nk, self.nao, self.nocc) or not C.is_contiguous():
-            raise ValueError(f"C must be contiguous with shape {(self.nk, self.nao, self.nocc)}")
+        if tuple(C.shape) != (self.nk, self.nao, self.ncol) or not C.is_contiguous():
+            raise ValueError(f"C must be contiguous with shape {(self.nk, self.nao, self.ncol)}")
 
     def build_device(self, C, K=None, Kmi=None, Ex=None):
         """occrik_build_device on caller tensors (asynchronous on the current stream)."""
         self._check_C(C)
-        for t, shape in ((K, (self.nk, self.nao, self.nao)), (Kmi, (self.nk, self.nao, self.nocc))):
+        for t, shape in ((K, (self.nk, self.nao, self.nao)), (Kmi, (self.nk, self.nao, self.ncol))):
             if t is not None and (t.dtype != torch.complex128 or tuple(t.shape) != shape or not t.is_contiguous()
                                   or t.device != self.device):
                 raise ValueError(f"output must be contiguous complex128 {shape} on the plan's device")
@@ -146,7 +150,7 @@ class Plan:
         """Build and return dict(K, Kmi, Ex) as device tensors; raises on a deferred device error."""
         dev = self.device
         K = torch.empty((self.nk, self.nao, self.nao), dtype=torch.complex128, device=dev) if want_K else None
-        Kmi = torch.empty((self.nk, self.nao, self.nocc), dtype=torch.complex128, device=dev) if want_Kmi else None
+        Kmi = torch.empty((self.nk, self.nao, self.ncol), dtype=torch.complex128, device=dev) if want_Kmi else None
         Ex = torch.empty((1,), dtype=torch.float64, device=dev)
         self.build_device(C, K, Kmi, Ex)
         self.status()
@@ -155,10 +159,10 @@ class Plan:
     def build_host(self, C: np.ndarray, want_K=True, want_Kmi=True):
         """occrik_build: synchronous, host arrays in and out."""
         C = np.ascontiguousarray(C, dtype=np.complex128)
-        if C.shape != (self.nk, self.nao, self.nocc):
+        if C.shape != (self.nk, self.nao, self.ncol):
             raise ValueError("bad C shape")
         K = np.empty((self.nk, self.nao, self.nao), np.complex128) if want_K else None
-        Kmi = np.empty((self.nk, self.nao, self.nocc), np.complex128) if want_Kmi else None
+        Kmi = np.empty((self.nk, self.nao, self.ncol), np.complex128) if want_Kmi else None
         Ex = ctypes.c_double(0.0)
         p = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
         self._sync_stream()
@@ -167,7 +171,7 @@ class Plan:
 
     def grad(self, gEx=1.0, want_C=True, want_omega=False):
         """occrik_grad after a build: dL/dC (device tensor) and dL/domega (float)."""
-        g = torch.empty((self.nk, self.nao, self.nocc), dtype=torch.complex128, device=self.device) if want_C else None
+        g = torch.empty((self.nk, self.nao, self.ncol), dtype=torch.complex128, device=self.device) if want_C else None
         dw = ctypes.c_double(0.0)
         self._sync_stream()
         check(self._lib.occrik_grad(self._h, float(gEx), ctypes.c_void_p(g.data_ptr()) if g is not None else None,
@@ -177,7 +181,7 @@ class Plan:
     # -- diagnostics and profiling -----------------------------------------------
     def intermediate(self, which: str):
         idx = {"chi": 0, "psi": 1, "W": 2}[which]
-        rows = self.nao if idx == 0 else self.nocc
+        rows = self.nao if idx == 0 else self.ncol
         out = torch.empty((self.nk, rows, self.ng), dtype=torch.complex128, device=self.device)
         self._sync_stream()
         check(self._lib.occrik_copy_intermediate(self._h, idx, ctypes.c_void_p(out.data_ptr()),

@@ -56,11 +56,11 @@ def _create(**override):
                        sl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        se.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     p = dict(kmesh=(1, 1, 1), grid=(8, 8, 8), nocc=1, kernel=0, omega=0.0, nyquist=1, precision=0,
-             lattice_tol=1e-12, kbatch=0, flags=0, mem_budget=0)
+             lattice_tol=1e-12, kbatch=0, flags=0, mem_budget=0, nvir=0)
     p.update(override)
     params = _lib.Params((ctypes.c_int32 * 3)(*p["kmesh"]), (ctypes.c_int32 * 3)(*p["grid"]), p["nocc"],
                          p["kernel"], p["omega"], p["nyquist"], p["precision"], p["lattice_tol"], p["kbatch"],
-                         p["flags"], p["mem_budget"])
+                         p["flags"], p["mem_budget"], p["nvir"])
     h = _lib.PlanP()
     st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params), 0, None,
                                 ctypes.byref(h))
@@ -73,6 +73,8 @@ def _create(**override):
     (dict(l=4), 2),                     # g functions are not supported
     (dict(nocc=0), 1),
     (dict(nocc=17), 1),
+    (dict(nvir=-1), 1),
+    (dict(nocc=10, nvir=7), 1),         # nocc + nvir above 16
     (dict(kernel=1, omega=0.0), 1),     # range-separated kernel without omega
     (dict(kernel=7), 1),
     (dict(precision=5), 1),

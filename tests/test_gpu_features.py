@@ -296,3 +296,49 @@ def test_integral_direct_switches_on_by_memory_budget_with_several_chunks():
         assert torch.equal(a[key], b[key]), key
     ref = occrik.build(prob, Cn, nyquist="symmetric")
     assert abs(float(b["Ex"][0]) - ref["Ex"]) < 1e-10 * abs(ref["Ex"])
+
+
+# ----------------------------------------------------------------------------
+# conduction-band extension (Sec. II.D): nvir extra columns treated exactly
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("grid,nocc,nvir,mode", [((12, 10, 9), 2, 2, "symmetric"), ((12, 10, 9), 2, 2, "fftfreq"),
+                                                 ((24, 24, 24), 3, 3, "symmetric"),
+                                                 ((24, 24, 24), 5, 6, "symmetric")])
+def test_conduction_bands_match_oracle(grid, nocc, nvir, mode):
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=grid, nocc=nocc + nvir, counts=(2, 2, 1), seed=17)
+    C = W.random_coefficients(prob)
+    chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+    ref = occrik.build(prob, C, chi=chi, nyquist=mode, nvir=nvir)
+    spec = PlanSpec.from_problem(prob, nocc=nocc, nvir=nvir, nyquist=1 if mode == "symmetric" else 0)
+    plan = Plan(spec)
+    out = plan.build(torch.from_numpy(C).to("cuda"))
+    Kmi, K, Ex = out["Kmi"].cpu().numpy(), out["K"].cpu().numpy(), float(out["Ex"][0])
+    assert np.max(np.abs(Kmi - ref["Kmi"])) < 1e-10 * np.max(np.abs(ref["Kmi"]))
+    assert np.max(np.abs(K - ref["K"])) < 1e-10 * np.max(np.abs(ref["K"]))
+    assert abs(Ex - ref["Ex"]) < 1e-10 * abs(ref["Ex"])
+    # gradient: (2/N_k) K_{mu j} on the occupied columns, zero on the bands
+    g, _ = plan.grad(1.0)
+    g = g.cpu().numpy()
+    assert np.max(np.abs(g[:, :, :nocc] - 2.0 / prob.nk * ref["Kmi"][:, :, :nocc])) < 1e-10 * np.max(np.abs(g))
+    assert np.all(g[:, :, nocc:] == 0)
+    # FP32-split on the same plan inputs
+    p32 = Plan(PlanSpec.from_problem(prob, nocc=nocc, nvir=nvir, precision=pkg.PREC_FP32_SPLIT,
+                                     nyquist=1 if mode == "symmetric" else 0))
+    o32 = p32.build(torch.from_numpy(C).to("cuda"))
+    assert abs(float(o32["Ex"][0]) - ref["Ex"]) <= 1e-6
+    assert np.max(np.abs(o32["K"].cpu().numpy() - ref["K"])) <= 1e-5
+
+
+def test_conduction_bands_leave_energy_and_omega_derivative_unchanged():
+    prob = W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=5, kernel=W.KERNEL_ERF_LR, omega=0.3)
+    C = W.random_coefficients(prob)
+    Ct = torch.from_numpy(C).to("cuda")
+    occ = Plan(PlanSpec.from_problem(prob, nocc=3))
+    ext = Plan(PlanSpec.from_problem(prob, nocc=3, nvir=2))
+    e_occ = float(occ.build(Ct[:, :, :3].contiguous())["Ex"][0])
+    e_ext = float(ext.build(Ct)["Ex"][0])
+    assert abs(e_occ - e_ext) < 1e-12 * abs(e_occ)
+    _, d_occ = occ.grad(1.0, want_C=False, want_omega=True)
+    _, d_ext = ext.grad(1.0, want_C=False, want_omega=True)
+    assert abs(d_occ - d_ext) < 1e-11 * abs(d_occ)
