@@ -237,6 +237,35 @@ occrik_status occrik_build(occrik_plan *plan, const double *C, double *K, double
  * non-NULL and a Cholesky fails, the K~ block of that k is left zeroed. */
 occrik_status occrik_build_device(occrik_plan *plan, const void *dC, void *dK, void *dKmi, double *dEx);
 
+/* Conventional GPW exchange on the plan's cell, grid, kernel and precision: the
+ * algorithms occ-RI-K is measured against, giving the full AO x AO exchange matrix
+ *   K_{nu mu}(k_2) = -(dV/N_k) sum_r conj(chi_{nu k_2}(r)) W_{mu k_2}(r)        (eq. aok)
+ * with, for every output AO mu of k_2, summed over k_1,
+ *   OCCRIK_ALGO_AO_RI_K  (Sec. II.B, Alg. 1): W_mu = sum_sigma psi~_{sigma k_1} V_{sigma k_1, mu k_2},
+ *       V fitted from conj(chi_{sigma k_1}) chi_{mu k_2} and
+ *       psi~_{sigma k} = sum_lambda P_{lambda sigma}(k) chi_{lambda k}, P = C C^H (eqs. aointerm, aointerm2);
+ *       N_k^2 N_ao^2 pair round trips
+ *   OCCRIK_ALGO_MO_RI_K  (Sec. II.C, Alg. 2): W_mu = sum_i psi_{i k_1} V_{i k_1, mu k_2},
+ *       V fitted from conj(psi_{i k_1}) chi_{mu k_2} (eqs. exxmo, mointerm2);
+ *       N_k^2 N_occ N_ao pair round trips
+ * (occ-RI-K: N_k^2 N_occ^2, halved with conjugate-pair reuse).  K C equals the K_{mu j}
+ * of a build and E_x is the same (Sec. II.D).
+ *   dC   [N_k][N_ao][nocc + nvir] complex128 device buffer; the first nocc columns
+ *        form the density
+ *   dK   [N_k][N_ao][N_ao] complex128 device buffer (required), row nu, column mu
+ *   dEx  device double (or NULL): (1/2N_k) sum_k Re tr(C_occ^H K C_occ)
+ * The pair passes, kernel multiply and contraction are those of occrik_build_device
+ * (same precision mode); workspaces are allocated on the plan at the first call
+ * (W of one k-point for every AO, the orbitals, and for AO-RI-K the [N_k][N_ao][N_g]
+ * density-contracted AOs).  Needs a plan with stored AOs (OCCRIK_ERR_UNSUPPORTED for
+ * integral-direct plans).  Asynchronous on the plan's stream; C is not checked for
+ * non-finite values. */
+enum {
+    OCCRIK_ALGO_AO_RI_K = 1,
+    OCCRIK_ALGO_MO_RI_K = 2
+};
+occrik_status occrik_conventional_k(occrik_plan *plan, int32_t algo, const void *dC, void *dK, double *dEx);
+
 /* Synchronise the plan's stream and return the deferred device status of the
  * last build (OCCRIK_OK, OCCRIK_ERR_NOT_PD or OCCRIK_ERR_NONFINITE). */
 occrik_status occrik_plan_status(occrik_plan *plan);

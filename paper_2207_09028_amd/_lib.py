@@ -25,6 +25,7 @@ FLAG_LDS_FFT = 1
 FLAG_REG_FFT_ALL = 2
 FLAG_DIRECT = 4
 FLAG_MADELUNG = 8
+ALGO_AO_RI_K, ALGO_MO_RI_K = 1, 2
 
 # every function the header declares, with (restype, argtypes)
 c_int32 = ctypes.c_int32
@@ -76,6 +77,7 @@ SIGNATURES = {
     "occrik_set_omega": (c_int32, [PlanP, c_double]),
     "occrik_build": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
     "occrik_build_device": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "occrik_conventional_k": (c_int32, [PlanP, c_int32, c_void_p, c_void_p, c_void_p]),
     "occrik_plan_status": (c_int32, [PlanP]),
     "occrik_last_error_k": (c_int32, [PlanP]),
     "occrik_grad": (c_int32, [PlanP, c_double, c_void_p, ctypes.POINTER(c_double)]),

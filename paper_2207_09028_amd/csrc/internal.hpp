@@ -43,6 +43,17 @@ struct PairBatch {
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
     int regfft;               // REGFFT_PASS* bits: passes run with register-resident line FFTs
     void* kvals;              // [nb][m2][m1][m3] kernel values of the batch, working precision (plan workspace)
+    // Orbital sources of the passes (working precision, complex).  The density of a
+    // slot is conj(D_{i b}) O_j and the a-side sum is W_j += A_{i b} Vt_ij, with
+    //   D_{i b} = psi[(b kstride + i) ng]   (the psi argument of the launchers)
+    //   O_j     = outp[j ng]                the output orbitals of k_a
+    //   A_{i b} = accp[(b kstride + i) ng]
+    // and W_j at W[woff + j ng] (the W argument).  occ-RI-K: D = A = psi~,
+    // O = psi~ at k_a, woff = a kstride ng.  The conventional algorithms pair the
+    // occupied orbitals (MO-RI-K) or the AOs (AO-RI-K) with a group of AOs of k_a.
+    const void* outp;
+    const void* accp;
+    size_t woff;
 };
 
 // pass-2 workgroups per m2-slab of a batch
@@ -110,6 +121,18 @@ hipError_t launch_scale_copy(const double2* src, double2* dst, size_t n, double 
 // dst[r][c] = scale * src[r][c] for c < nkeep, 0 for nkeep <= c < ncol
 hipError_t launch_grad_columns(const double2* src, double2* dst, size_t rows, int ncol, int nkeep, double scale,
                                hipStream_t s);
+
+// Conventional algorithms (AO-RI-K, MO-RI-K).
+// psit[k][sigma][n] = sum_{i < nocc} conj(C[k][sigma][i]) psi[k][i][n]; C and psi have ncol columns
+template <typename T>
+hipError_t launch_density_orbitals(const double2* C, const cplx<T>* psi, cplx<T>* psit, int nk, int nao, int ncol,
+                                   int nocc, int ng, hipStream_t s);
+// dst[r ld + col0 + j] = scale * sum_c Kpart[(r ncols + j) nchunks + c], c in chunk order
+hipError_t launch_reduce_columns(const double2* Kpart, double2* dst, int rows, int ncols, int ld, int col0,
+                                 int nchunks, double scale, hipStream_t s);
+// eterm[k] = Re tr(C^H K C) / (2 N_k) over the first nocc of the ncol columns of C
+hipError_t launch_conv_energy(const double2* C, const double2* K, double* eterm, int nk, int nao, int ncol, int nocc,
+                              hipStream_t s);
 
 // Collocation: at plan time into the stored chi~, or per build and per grid chunk in
 // integral-direct plans; both run the same per-point arithmetic.

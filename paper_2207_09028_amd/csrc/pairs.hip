@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
     int b, i, j;
     decode_slot(B, slot, b, i, j);
     load_twiddles<T>(tw, twg);
-    const cplx<T>* pj = psi + ((size_t)B.a * B.kstride + j) * B.ng + (size_t)n1 * plane_sz;
+    const cplx<T>* pj = static_cast<const cplx<T>*>(B.outp) + (size_t)j * B.ng + (size_t)n1 * plane_sz;
     const cplx<T>* pi = psi + ((size_t)b * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
     constexpr int PTS = ((NN > 0 ? NN * NN : kMaxN * kMaxN) + kFftThreads - 1) / kFftThreads;
 #pragma unroll
@@ -241,7 +241,6 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
 // ---------------------------------------------------------------------------
 template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const cplx<T>* __restrict__ X,
-                                                            const cplx<T>* __restrict__ psi,
                                                             cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
                                                             const cplx<T>* __restrict__ twg) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -307,7 +306,8 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
             } else {
                 slot = full_base + (bb - first_full) * nn + i * B.nout + j;
             }
-            const cplx<T>* pi = psi + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
+            const cplx<T>* pi = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng +
+                                (size_t)n1 * plane_sz;
             term(slot, cj, pi, n1);
         }
         cplx<T>* out = Wpart + ((size_t)s * B.nout + j) * B.ng + (size_t)n1 * plane_sz;
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
         const int bb = first_full + blk;
         for (int j = 0; j < B.nocc; ++j) {
             const int slot = full_base + blk * nn + i * B.nout + j;
-            const cplx<T>* pj = psi + ((size_t)B.a * B.kstride + j) * B.ng + (size_t)n1 * plane_sz;
+            const cplx<T>* pj = static_cast<const cplx<T>*>(B.outp) + (size_t)j * B.ng + (size_t)n1 * plane_sz;
             term(slot, true, pj, n1);
         }
         cplx<T>* out = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * plane_sz;
@@ -365,7 +365,6 @@ constexpr int pow2_at_least(int n) {
 
 template <typename T, int NN, int JC>
 __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, const cplx<T>* __restrict__ X,
-                                                             const cplx<T>* __restrict__ psi,
                                                              cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
                                                              const cplx<T>* __restrict__ twg) {
     constexpr int WB = colblock(NN, (int)sizeof(cplx<T>));
@@ -425,7 +424,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     // spill): the next pair's column is loaded while this pair is transformed, and the
     // a-side orbital at this thread's points, the same for every summed pair, is held.
     constexpr bool PF = JC <= 8;
-    const cplx<T>* pa_src = psi + ((size_t)B.a * B.kstride + (active ? jl : 0)) * B.ng + plane_off;
+    const cplx<T>* pa_src = static_cast<const cplx<T>*>(B.outp) + (size_t)(active ? jl : 0) * B.ng + plane_off;
     cplx<T> pa[PT];
     if constexpr (PF) {
 #pragma unroll
@@ -454,7 +453,7 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
         // in flight during this pair's transform: the next pair's column, this pair's
         // b-side orbital values and its W block
         if (PF && q + 1 < q1) load_column(q + 1, xn);
-        const cplx<T>* ui_src = psi + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
+        const cplx<T>* ui_src = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
         cplx<T> ui[PT];
         if constexpr (PF) {
 #pragma unroll
@@ -520,7 +519,7 @@ __global__ void wreduce_kernel(PairBatch B, const cplx<T>* __restrict__ Wpart, c
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t tot = (size_t)B.nout * B.ng;               // partials: [split][nout][ng]
     if (n >= tot) return;
-    cplx<T>* w = W + (size_t)B.a * B.kstride * B.ng;        // the output orbitals at k_a
+    cplx<T>* w = W + B.woff;                                // the output orbitals at k_a
     cplx<T> acc = w[n];
     for (int s = 0; s < B.splits; ++s) acc = cadd<T>(acc, Wpart[(size_t)s * tot + n]);
     w[n] = acc;
@@ -626,19 +625,19 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
         const size_t lds = sizeof(cplx<T>) * (3 * kMaxN + (size_t)nnv * lnp);
         if (jc == 8) {
             OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 8>), dim3(grid),
-                                                                       dim3(kPass3Threads), lds, s, B, X, psi,
-                                                                       Wpart, W, tw));
+                                                                       dim3(kPass3Threads), lds, s, B, X, Wpart,
+                                                                       W, tw));
         } else {
             OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 16>), dim3(grid),
-                                                                       dim3(kPass3Threads), lds, s, B, X, psi,
-                                                                       Wpart, W, tw));
+                                                                       dim3(kPass3Threads), lds, s, B, X, Wpart,
+                                                                       W, tw));
         }
         return hipGetLastError();
     }
     const int nfull_b = B.reuse ? B.nb - (B.diag ? 1 : 0) : 0;
     const unsigned grid = (unsigned)((size_t)B.N1 * B.nout * B.splits + (size_t)nfull_b * B.nocc * B.N1);
     const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
-    hipLaunchKernelGGL((pass3_kernel<T, 0>), dim3(grid), dim3(kFftThreads), lds, s, B, X, psi, Wpart, W, tw);
+    hipLaunchKernelGGL((pass3_kernel<T, 0>), dim3(grid), dim3(kFftThreads), lds, s, B, X, Wpart, W, tw);
     return hipGetLastError();
 }
 

@@ -56,6 +56,10 @@ struct DeviceGuard {
     }
 };
 
+// output AOs of k_a per group of the conventional pair passes (the occ-RI-K pass-3
+// tile of eight output orbitals, with the next pair prefetched)
+constexpr int kConvGroup = 8;
+
 struct ProfileEvents {
     hipEvent_t e[5];
     int64_t pair_launches;
@@ -105,6 +109,16 @@ struct occrik_plan {
     double madelung_g0 = 0.0;  // Madelung mode: N_k Omega M_s of the k-mesh supercell (0: off)
     void* chi_ws = nullptr;    // direct: [nk][nao][cchunk] chi~ of one chunk
     bool regfft = false;       // complex64 pair passes with register-resident transforms
+    // conventional algorithms (AO-RI-K, MO-RI-K): workspaces allocated on first use
+    int conv_kbatch = 0;       // (a, b) blocks per batch of the conventional pair passes
+    int conv_nsum = 0;         // summed orbitals the X workspace is sized for
+    void* conv_psi = nullptr;  // [nk][nout][ng] occupied orbitals of the conventional call
+    void* conv_psit = nullptr; // AO-RI-K: [nk][nao][ng] density-contracted AOs (eq. aointerm)
+    void* conv_W = nullptr;    // [nao][ng] W of every AO of one output k-point
+    void* conv_X = nullptr;    // [conv_kbatch * conv_nsum * kConvGroup][ng]
+    void* conv_Wpart = nullptr;  // [splits][kConvGroup][ng]
+    void* conv_kvals = nullptr;  // [conv_kbatch][ng]
+    double2* conv_Kpart = nullptr;  // [nao][16][nchunks]
     double2* Kpart = nullptr;  // [nk][nao][nout][nchunks]
     double2* Kmi = nullptr;    // [nk][nao][nout]
     double2* Kij = nullptr;    // [nk][nout][nout]
@@ -474,6 +488,10 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb, bool occ_only 
                : (P->params.flags & OCCRIK_FLAG_REG_FFT_ALL) ? (REGFFT_PASS1 | REGFFT_PASS2 | REGFFT_PASS3)
                                                               : REGFFT_DEFAULT;
     B.kvals = P->kvals;
+    const char* psi = static_cast<const char*>(P->psi);
+    B.outp = psi + (size_t)a * B.kstride * B.ng * P->elem;
+    B.accp = psi;
+    B.woff = (size_t)a * B.kstride * B.ng;
     return B;
 }
 
@@ -592,6 +610,137 @@ occrik_status domega_impl(occrik_plan* P, double* out_host) {
         }
     OCCRIK_HIP(hipMemcpyAsync(out_host, P->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     OCCRIK_HIP(hipStreamSynchronize(s));
+    return OCCRIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// conventional exchange: AO-RI-K (Sec. II.B, Alg. 1) and MO-RI-K (Sec. II.C, Alg. 2)
+// ---------------------------------------------------------------------------
+// Pair passes of output k-point a, output AOs [j0, j0 + g), summed k-points [b0, b0 + nb).
+// MO-RI-K: densities conj(psi_{i b}) chi_{mu a}, W_mu += psi_{i b} V (eq. mointerm2).
+// AO-RI-K: densities conj(chi_{sigma b}) chi_{mu a}, V~_mu += psi~_{sigma b} V (eq. aointerm2).
+PairBatch make_conv_batch(const occrik_plan* P, int algo, int a, int j0, int g, int b0, int nb) {
+    PairBatch B{};
+    B.N1 = P->N[0];
+    B.N2 = P->N[1];
+    B.N3 = P->N[2];
+    B.ng = P->ng;
+    B.M1 = P->M[0];
+    B.M2 = P->M[1];
+    B.M3 = P->M[2];
+    const bool ao = algo == OCCRIK_ALGO_AO_RI_K;
+    B.nocc = ao ? P->nao : P->nocc;
+    B.nout = g;
+    B.kstride = ao ? P->nao : P->nout;
+    B.a = a;
+    B.b0 = b0;
+    B.nb = nb;
+    B.reuse = 0;
+    B.diag = 0;
+    B.ntri = B.nocc * (B.nocc + 1) / 2;
+    B.nslots = nb * B.nocc * g;
+    B.group = g;
+    B.kernel = P->params.kernel;
+    B.nyquist = P->params.nyquist;
+    B.omega = P->params.omega;
+    B.rcut = std::cbrt(3.0 * double(P->nk) * P->volume / (4.0 * M_PI));
+    B.madelung = P->madelung_g0 != 0.0 ? 1 : 0;
+    B.g0 = P->madelung_g0;
+    B.inv_ng = 1.0 / P->ng;
+    std::memcpy(B.recip, P->recip, sizeof(B.recip));
+    B.splits = pass3_splits(B, (int)P->elem);
+    B.parseval = 0;
+    B.regfft = 0;
+    B.kvals = P->conv_kvals;
+    const size_t e = P->elem;
+    B.outp = static_cast<const char*>(P->chi) + ((size_t)a * P->nao + j0) * P->ng * e;
+    B.accp = ao ? P->conv_psit : P->conv_psi;
+    B.woff = (size_t)j0 * P->ng;
+    return B;
+}
+
+// workspaces of the conventional passes, grown on demand
+occrik_status conv_workspace(occrik_plan* P, int algo) {
+    const int nk = P->nk, nao = P->nao, ng = P->ng;
+    const size_t e = P->elem;
+    const int nsum = algo == OCCRIK_ALGO_AO_RI_K ? nao : P->nocc;
+    hipError_t err = hipSuccess;
+    auto A = [&](void** p, size_t bytes) {
+        if (err == hipSuccess && *p == nullptr) err = P->alloc(p, bytes);
+    };
+    A(&P->conv_psi, (size_t)nk * P->nout * ng * e);
+    A(&P->conv_W, (size_t)nao * ng * e);
+    A((void**)&P->conv_Kpart, sizeof(double2) * (size_t)nao * 16 * P->nchunks);
+    if (algo == OCCRIK_ALGO_AO_RI_K) A(&P->conv_psit, (size_t)nk * nao * ng * e);
+    if (err != hipSuccess) return hip_fail(err, "conventional workspace");
+    if (nsum > P->conv_nsum) {
+        P->release(P->conv_X);
+        P->release(P->conv_Wpart);
+        P->release(P->conv_kvals);
+        P->conv_X = P->conv_Wpart = P->conv_kvals = nullptr;
+        const size_t per_block = (size_t)nsum * kConvGroup * ng * e;
+        const size_t cap = (size_t)4 << 30;
+        P->conv_kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_block));
+        PairBatch B = make_conv_batch(P, algo, 0, 0, kConvGroup, 0, P->conv_kbatch);
+        A(&P->conv_X, (size_t)P->conv_kbatch * per_block);
+        A(&P->conv_Wpart, (size_t)B.splits * kConvGroup * ng * e);
+        A(&P->conv_kvals, e / 2 * (size_t)P->conv_kbatch * ng);
+        if (err != hipSuccess) {
+            P->conv_nsum = 0;
+            return hip_fail(err, "conventional workspace");
+        }
+        P->conv_nsum = nsum;
+    }
+    return OCCRIK_OK;
+}
+
+template <typename T>
+occrik_status conventional_impl(occrik_plan* P, int algo, const double2* dC, double2* dK, double* dEx) {
+    hipStream_t s = P->stream;
+    const int nk = P->nk, nao = P->nao, ng = P->ng, ncol = P->nout;
+    occrik_status st = conv_workspace(P, algo);
+    if (st != OCCRIK_OK) return st;
+    const cplx<T>* chi = reinterpret_cast<const cplx<T>*>(P->chi);
+    cplx<T>* psi = reinterpret_cast<cplx<T>*>(P->conv_psi);
+    cplx<T>* Wa = reinterpret_cast<cplx<T>*>(P->conv_W);
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(P->conv_X);
+    cplx<T>* Wp = reinterpret_cast<cplx<T>*>(P->conv_Wpart);
+    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(P->tw);
+    const bool ao = algo == OCCRIK_ALGO_AO_RI_K;
+    // eq. occmo, then (AO-RI-K) eq. aointerm
+    OCCRIK_HIP(launch_orbitals<T>(chi, (size_t)ng, dC, psi, nk, nao, ncol, ng, 0, ng, P->params.precision, s));
+    if (ao)
+        OCCRIK_HIP(launch_density_orbitals<T>(dC, psi, reinterpret_cast<cplx<T>*>(P->conv_psit), nk, nao, ncol,
+                                              P->nocc, ng, s));
+    // the summed side's densities: occupied orbitals (MO-RI-K) or AOs (AO-RI-K)
+    const cplx<T>* dens = ao ? chi : psi;
+    for (int a = 0; a < nk; ++a) {
+        OCCRIK_HIP(launch_fill_zero<T>(Wa, (size_t)nao * ng, s));
+        for (int j0 = 0; j0 < nao; j0 += kConvGroup) {
+            const int g = std::min(kConvGroup, nao - j0);
+            for (int b0 = 0; b0 < nk; b0 += P->conv_kbatch) {
+                const int nb = std::min(P->conv_kbatch, nk - b0);
+                const PairBatch B = make_conv_batch(P, algo, a, j0, g, b0, nb);
+                OCCRIK_HIP(launch_pass1<T>(B, dens, X, tw, s));
+                OCCRIK_HIP(launch_pass2<T>(B, X, tw, P->parts, 0, s));
+                OCCRIK_HIP(launch_pass3<T>(B, X, dens, Wp, Wa, tw, s));
+                OCCRIK_HIP(launch_wreduce<T>(B, Wp, Wa, s));
+            }
+        }
+        // eq. aok: K_{nu mu}(k_a) = -(dV/N_k) sum_r conj(chi_{nu a}) W_mu, 16 columns per contraction
+        const cplx<T>* chia = chi + (size_t)a * nao * ng;
+        for (int j0 = 0; j0 < nao; j0 += 16) {
+            const int g = std::min(16, nao - j0);
+            OCCRIK_HIP(launch_contract_part<T>(chia, (size_t)ng, 0, Wa + (size_t)j0 * ng, P->conv_Kpart, 1, nao, g,
+                                               ng, P->nchunks, 0, P->nchunks, P->params.precision, s));
+            OCCRIK_HIP(launch_reduce_columns(P->conv_Kpart, dK + (size_t)a * nao * nao, nao, g, nao, j0,
+                                             P->nchunks, -P->dv / nk, s));
+        }
+    }
+    if (dEx) {
+        OCCRIK_HIP(launch_conv_energy(dC, dK, P->eterm, nk, nao, ncol, P->nocc, s));
+        OCCRIK_HIP(launch_energy(P->eterm, nk, dEx, s));
+    }
     return OCCRIK_OK;
 }
 
@@ -878,6 +1027,16 @@ occrik_status occrik_build_device(occrik_plan* P, const void* dC, void* dK, void
     P->last_err_k = -1;
     return P->fp64 ? build_impl<double>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx)
                    : build_impl<float>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx);
+}
+
+occrik_status occrik_conventional_k(occrik_plan* P, int32_t algo, const void* dC, void* dK, double* dEx) {
+    if (!P || !dC || !dK) return fail(OCCRIK_ERR_INVALID_ARG, "null plan, C or K");
+    if (algo != OCCRIK_ALGO_AO_RI_K && algo != OCCRIK_ALGO_MO_RI_K)
+        return fail(OCCRIK_ERR_INVALID_ARG, "algo must be OCCRIK_ALGO_AO_RI_K or OCCRIK_ALGO_MO_RI_K");
+    if (P->direct) return fail(OCCRIK_ERR_UNSUPPORTED, "the conventional algorithms need the stored Bloch AOs");
+    DeviceGuard guard(P->device);
+    return P->fp64 ? conventional_impl<double>(P, algo, (const double2*)dC, (double2*)dK, dEx)
+                   : conventional_impl<float>(P, algo, (const double2*)dC, (double2*)dK, dEx);
 }
 
 occrik_status occrik_plan_status(occrik_plan* P) {

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check
+from ._lib import ALGO_AO_RI_K, ALGO_MO_RI_K, check
 
 
 def _stream_handle(device):
@@ -155,6 +155,29 @@ class Plan:
         self.build_device(C, K, Kmi, Ex)
         self.status()
         return dict(K=K, Kmi=Kmi, Ex=Ex)
+
+    def conventional_k(self, C, algo="mo", K=None, Ex=None):
+        """occrik_conventional_k: the full AO x AO exchange matrix by MO-RI-K (Alg. 2,
+        ``algo="mo"``) or AO-RI-K (Alg. 1, ``algo="ao"``) on this plan's grid and kernel.
+        Returns dict(K, Ex) as device tensors; asynchronous on the current stream."""
+        code = {"ao": ALGO_AO_RI_K, "mo": ALGO_MO_RI_K}.get(algo)
+        if code is None:
+            raise ValueError("algo must be 'ao' or 'mo'")
+        self._check_C(C)
+        dev = self.device
+        shape = (self.nk, self.nao, self.nao)
+        if K is None:
+            K = torch.empty(shape, dtype=torch.complex128, device=dev)
+        elif K.dtype != torch.complex128 or tuple(K.shape) != shape or not K.is_contiguous() or K.device != dev:
+            raise ValueError(f"K must be contiguous complex128 {shape} on the plan's device")
+        if Ex is None:
+            Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        elif Ex.dtype != torch.float64 or Ex.numel() != 1 or Ex.device != dev:
+            raise ValueError("Ex must be one float64 on the plan's device")
+        self._sync_stream()
+        check(self._lib.occrik_conventional_k(self._h, code, ctypes.c_void_p(C.data_ptr()),
+                                              ctypes.c_void_p(K.data_ptr()), ctypes.c_void_p(Ex.data_ptr())), self._h)
+        return dict(K=K, Ex=Ex)
 
     def build_host(self, C: np.ndarray, want_K=True, want_Kmi=True):
         """occrik_build: synchronous, host arrays in and out."""

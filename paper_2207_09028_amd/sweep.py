@@ -1,0 +1,139 @@
+"""Timing sweeps of the three exchange algorithms on one device.
+
+The paper's timing benchmark (Sec. III) times one exchange-matrix build of
+diamond with AO-RI-K (Alg. 1), MO-RI-K (Alg. 2) and occ-RI-K (Alg. 3) as the
+k-mesh grows, and occ-RI-K alone as the basis grows at a 6x6x6 mesh.  These
+sweeps repeat both on the device, all three algorithms through the same pair
+passes, kernel multiply and contraction:
+
+  python -m paper_2207_09028_amd.sweep kmesh [--precision fp32split] [--grid 24] [--cap 30]
+  python -m paper_2207_09028_amd.sweep basis [--precision fp32split] [--cap 30]
+
+Inputs are synthetic: the 2-atom diamond cell with even-tempered uncontracted
+bases and seeded S-orthonormal occupied coefficients.  Each output line is one
+JSON record (algorithm, sizes, pair round trips, ms per build).  A run whose
+time, predicted from the algorithm's last measured rate per pair round trip,
+exceeds ``--cap`` seconds is reported as skipped.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+import workloads as W
+
+from . import NYQUIST_SYMMETRIC, PREC_FP32, PREC_FP32_SPLIT, PREC_FP64
+from .plan import Plan, PlanSpec
+
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp32split": PREC_FP32_SPLIT}
+
+# per-atom shell counts (s, p, d, f) of the basis sweep and their AO counts for 2 atoms
+BASIS_LADDER = [(4, 3), (5, 3, 1), (8, 8, 3), (10, 10, 5, 3), (20, 15, 10, 5)]
+
+
+def round_trips(algo: str, nk: int, nao: int, nocc: int) -> int:
+    """Pair round trips of one build (occ-RI-K with conjugate-pair reuse)."""
+    if algo == "occ":
+        return nk * nocc * (nk * nocc + 1) // 2
+    if algo == "mo":
+        return nk * nk * nocc * nao
+    return nk * nk * nao * nao
+
+
+def time_build(plan: Plan, Ct: torch.Tensor, algo: str, reps: int) -> tuple[float, float]:
+    """(ms per build, E_x) over ``reps`` builds after one warm-up, timed with events."""
+    dev = Ct.device
+    K = torch.empty((plan.nk, plan.nao, plan.nao), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    Kmi = torch.empty((plan.nk, plan.nao, plan.ncol), dtype=torch.complex128, device=dev)
+
+    def once():
+        if algo == "occ":
+            plan.build_device(Ct, K, Kmi, Ex)
+        else:
+            plan.conventional_k(Ct, algo=algo, K=K, Ex=Ex)
+
+    once()
+    torch.cuda.synchronize()
+    if algo == "occ":
+        plan.status()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        once()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps, float(Ex[0])
+
+
+def run_point(prob: W.Problem, algos, precision: int, reps: int, cap: float, rates: dict, tag: dict):
+    C = W.random_coefficients(prob)
+    Ct = torch.from_numpy(C).to("cuda")
+    t0 = time.perf_counter()
+    plan = Plan(PlanSpec.from_problem(prob, precision=precision, nyquist=NYQUIST_SYMMETRIC))
+    plan_s = time.perf_counter() - t0
+    for algo in algos:
+        rt = round_trips(algo, prob.nk, prob.nao, prob.nocc)
+        rec = dict(tag, algo=algo, nk=prob.nk, nao=prob.nao, nocc=prob.nocc, grid=list(prob.grid),
+                   round_trips=rt, plan_s=round(plan_s, 3))
+        if algo in rates and rates[algo] * rt * (reps + 1) > cap * 1e3:
+            rec["skipped"] = f"predicted {rates[algo] * rt / 1e3:.1f} s per build"
+        else:
+            ms, ex = time_build(plan, Ct, algo, reps)
+            rates[algo] = ms / rt
+            rec.update(ms_per_build=round(ms, 3), Ex=ex)
+        print(json.dumps(rec), flush=True)
+    plan.close()
+    del Ct
+    torch.cuda.empty_cache()
+
+
+def sweep_kmesh(args):
+    rates: dict = {}
+    for m in range(1, args.max_mesh + 1):
+        prob = W.Problem(f"kmesh{m}", W.diamond_cell(), W.even_tempered_basis(2, list(args.counts), 0.15, 12.0),
+                         (m, m, m), (args.grid,) * 3, args.nocc, seed=100 + m)
+        run_point(prob, ("occ", "mo", "ao"), PRECISIONS[args.precision], args.reps, args.cap, rates,
+                  dict(sweep="kmesh", precision=args.precision))
+
+
+def sweep_basis(args):
+    rates_big: dict = {}
+    rates_small: dict = {}
+    for counts in BASIS_LADDER:
+        basis = W.even_tempered_basis(2, list(counts), 0.05, 50.0)
+        big = W.Problem("basis", W.diamond_cell(), basis, (6, 6, 6), (48, 48, 48), 8, seed=200)
+        run_point(big, ("occ",), PRECISIONS[args.precision], args.reps, args.cap, rates_big,
+                  dict(sweep="basis", precision=args.precision, counts=list(counts)))
+        small = W.Problem("basis", W.diamond_cell(), basis, (2, 2, 2), (48, 48, 48), 8, seed=201)
+        run_point(small, ("occ", "mo", "ao"), PRECISIONS[args.precision], args.reps, args.cap, rates_small,
+                  dict(sweep="basis", precision=args.precision, counts=list(counts)))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("which", choices=("kmesh", "basis"))
+    ap.add_argument("--precision", choices=tuple(PRECISIONS), default="fp32split")
+    ap.add_argument("--grid", type=int, default=24, help="grid points per direction (kmesh sweep)")
+    ap.add_argument("--counts", type=int, nargs="+", default=[4, 3],
+                    help="shells per angular momentum per atom (kmesh sweep)")
+    ap.add_argument("--nocc", type=int, default=4, help="occupied orbitals (kmesh sweep)")
+    ap.add_argument("--max-mesh", type=int, default=6, help="largest M of the M x M x M meshes")
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--cap", type=float, default=30.0, help="seconds; longer runs are skipped")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("the sweeps need a GPU", file=sys.stderr)
+        return 2
+    np.set_printoptions(precision=4)
+    (sweep_kmesh if args.which == "kmesh" else sweep_basis)(args)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
