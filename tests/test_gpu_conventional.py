@@ -97,8 +97,8 @@ def test_conventional_fp32_split_meets_the_accuracy_gate():
 def test_conventional_uses_the_occupied_columns_of_an_extended_plan():
     prob, C, chi = _case((12, 10, 9), 5, (2, 1, 1))
     Ct = torch.from_numpy(C).to("cuda")
-    ext = Plan(PlanSpec.from_problem(prob, nocc=3, nvir=2))
-    occ = Plan(PlanSpec.from_problem(prob, nocc=3))
+    ext = Plan(PlanSpec.from_problem(prob, nocc=3, nvir=2, nyquist=0))
+    occ = Plan(PlanSpec.from_problem(prob, nocc=3, nyquist=0))
     Ke = ext.conventional_k(Ct, algo="mo")["K"].cpu().numpy()
     Ko = occ.conventional_k(Ct[:, :, :3].contiguous(), algo="mo")["K"].cpu().numpy()
     assert _rel(Ke, Ko) < 1e-14
