@@ -241,6 +241,69 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, int lines, int es, int l
     if constexpr (S::r2 != 0) stockham_stage<T, N, S::r2, S::r0 * S::r1, DIR, LINES, NT>(buf, lines, es, ls, tw);
 }
 
+// ---------------------------------------------------------------------------
+// Two-stage lengths N = R0 R1 with the stages exposed, for kernels that feed the
+// first stage from registers, keep the second stage's outputs in registers, or
+// alternate two LDS buffers.  Stage A (radix R0, no twiddles): item (line, j),
+// j < R1, inputs at elements j + r R1 (r < R0), outputs at j R0 + r.  Stage B
+// (radix R1, twiddles w_N^{j r}): item (line, j), j < R0, inputs and outputs at
+// the same elements j + r R0 (r < R1), so stage B runs in place.  A then B is
+// the Stockham transform of fft_lines; output in natural order.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Split2 {
+    static constexpr int R0 = Sched<N>::r0;
+    static constexpr int R1 = Sched<N>::r1;
+    static_assert(Sched<N>::r2 == 0 && Sched<N>::r1 > 0, "two-stage lengths only");
+};
+
+// stage A on v[R0] (inputs in v), outputs stored at elements j R0 + r of a line
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void stage_a_store(cplx<T>* v, cplx<T>* line, int j, int es) {
+    constexpr int R0 = Split2<N>::R0;
+    Dft<T, R0, DIR>::run(v);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) line[(j * R0 + r) * es] = v[r];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stage_a_load(cplx<T>* v, const cplx<T>* line, int j, int es) {
+    constexpr int R0 = Split2<N>::R0, R1 = Split2<N>::R1;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = line[(j + r * R1) * es];
+}
+
+// stage B twiddles of item j for the forward table tw[t] = e^{-2 pi i t / N}
+template <typename T, int N>
+__device__ __forceinline__ void stage_b_twiddles(cplx<T>* w, const cplx<T>* tw, int j) {
+    constexpr int R1 = Split2<N>::R1;
+#pragma unroll
+    for (int r = 1; r < R1; ++r) w[r - 1] = tw[j * r];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stage_b_load(cplx<T>* v, const cplx<T>* line, int j, int es) {
+    constexpr int R0 = Split2<N>::R0, R1 = Split2<N>::R1;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = line[(j + r * R0) * es];
+}
+
+// stage B on v[R1] with the item's forward twiddles w (conjugated for DIR = +1)
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void stage_b(cplx<T>* v, const cplx<T>* w) {
+    constexpr int R1 = Split2<N>::R1;
+#pragma unroll
+    for (int r = 1; r < R1; ++r) v[r] = DIR < 0 ? cmul<T>(v[r], w[r - 1]) : cjmul<T>(w[r - 1], v[r]);
+    Dft<T, R1, DIR>::run(v);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stage_b_store(const cplx<T>* v, cplx<T>* line, int j, int es) {
+    constexpr int R0 = Split2<N>::R0, R1 = Split2<N>::R1;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) line[(j + r * R0) * es] = v[r];
+}
+
 // Run-time length dispatch for grids without a compile-time specialisation.
 // Each length is a separate out-of-line function so that the caller does not
 // carry the register footprint of every length at once.

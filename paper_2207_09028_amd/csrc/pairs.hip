@@ -236,6 +236,174 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
     }
 }
 
+// Pass 2 for the compiled cubic sizes (N = R0 R1): the slab transforms run as
+// two-stage Stockham lines with stage A fed from the registers the global
+// prefetch filled, the kernel multiply applied to the forward stage B outputs
+// in registers, and the last inverse stage B stored straight to device memory
+// (lanes along n3: coalesced).  Two LDS buffers alternate so that a stage A
+// reads one and writes the other; stage B works in place.  Per pair: 5
+// barriers and 10 LDS accesses per point (the single-buffer form takes 15 and 16).
+template <int NN>
+struct P2S {
+    static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
+    static constexpr int NA = NN * R1;                  // stage A items of a slab (line-fastest)
+    static constexpr int NBI = NN * R0;                 // stage B items
+    static constexpr int NT = ((NA > NBI ? NA : NBI) + 63) / 64 * 64;
+    static constexpr int S = NN + 1;                    // padded row of the slab in LDS
+};
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T>* __restrict__ X,
+                                                             const cplx<T>* __restrict__ twg,
+                                                             double* __restrict__ parts, int deriv_only) {
+    using C = P2S<NN>;
+    constexpr int R0 = C::R0, R1 = C::R1, S = C::S, NT = C::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);
+    cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(red + NT);
+    cplx<T>* buf1 = buf0 + NN * S;
+    const int m2i = blockIdx.x % NN;
+    const int grp = blockIdx.x / NN;
+    const int P = B.group;
+    const int nn = B.nocc * B.nout;
+    const int gd = B.diag ? (B.ntri + P - 1) / P : 0;
+    const int go = (nn + P - 1) / P;
+    int s0, s1, b;
+    if (grp < gd) {
+        s0 = grp * P;
+        s1 = min(B.ntri, s0 + P);
+        b = B.a;
+    } else {
+        const int g = grp - gd;
+        const int blk = g / go;
+        const int base = (B.diag ? B.ntri : 0) + blk * nn;
+        s0 = base + (g - blk * go) * P;
+        s1 = min(base + nn, s0 + P);
+        b = B.b0 + (B.diag ? 1 : 0) + blk;
+    }
+    const int tid = threadIdx.x;
+    const bool ha = tid < C::NA, hb = tid < C::NBI;
+    const int aj = tid / NN, al = tid - aj * NN;        // stage A item (line al, index aj)
+    const int bj = tid / NN, bl = al;                   // stage B item (line bl, index bj)
+    constexpr size_t rs = (size_t)NN * NN;              // n1 stride of a pair's spectrum
+    // stage B twiddles and this item's kernel values (element (m1, m3) = (bj + r R0, bl))
+    cplx<T> w[R1 - 1];
+    T v[R1];
+    {
+        const T* kv = static_cast<const T*>(B.kvals) + ((size_t)(b - B.b0) * NN + m2i) * rs;
+        if (hb) {
+            stage_b_twiddles<T, NN>(w, twg, bj);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = kv[(size_t)(bj + r * R0) * NN + bl];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = T(0);
+#pragma unroll
+            for (int r = 0; r < R1 - 1; ++r) w[r] = mk<T>(T(0), T(0));
+        }
+    }
+    const T scale = T(B.inv_ng);
+    double acc = 0.0;
+    // stage A inputs of the forward n1 transform: elements n1 = aj + r R1 of line m3 = al
+    cplx<T> xn[R0];
+    auto load_slab = [&](int sl) {
+        const cplx<T>* src = X + (size_t)sl * B.ng + (size_t)m2i * NN + al;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) xn[r] = ha ? src[(size_t)(aj + r * R1) * rs] : mk<T>(T(0), T(0));
+    };
+    load_slab(s0);
+    cplx<T>* Pb = buf0;
+    cplx<T>* Qb = buf1;
+    for (int slot = s0; slot < s1; ++slot) {
+        double wgt = 1.0;
+        if (B.reuse) {
+            if (b != B.a) wgt = 2.0;
+            else {
+                int bb, ii, jj;
+                decode_slot(B, slot, bb, ii, jj);
+                wgt = ii == jj ? 1.0 : 2.0;
+            }
+        }
+        // forward along n1 (lines m3, elements n1 at stride S): stage A from registers
+        if (ha) {
+            cplx<T> a[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) a[r] = xn[r];
+            stage_a_store<T, NN, -1>(a, Pb + al, aj, S);
+        }
+        if (slot + 1 < s1) load_slab(slot + 1);
+        __syncthreads();
+        double pacc = 0.0;
+        if (hb) {
+            cplx<T> u[R1];
+            stage_b_load<T, NN>(u, Pb + bl, bj, S);
+            stage_b<T, NN, -1>(u, w);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                if (deriv_only || B.parseval)
+                    pacc += double(v[r]) * (double(u[r].x) * double(u[r].x) + double(u[r].y) * double(u[r].y));
+                u[r] = cscale<T>(u[r], v[r] * scale);
+            }
+            if (!deriv_only) stage_b_store<T, NN>(u, Pb + bl, bj, S);
+        }
+        acc += wgt * pacc;
+        if (deriv_only) {
+            // the next pair's stage A writes the other buffer while this one is read
+            cplx<T>* t = Pb;
+            Pb = Qb;
+            Qb = t;
+            continue;
+        }
+        __syncthreads();
+        // inverse along m3 (lines m1 at stride S, elements m3 adjacent): P -> Q
+        if (ha) {
+            cplx<T> a[R0];
+            stage_a_load<T, NN>(a, Pb + al * S, aj, 1);
+            stage_a_store<T, NN, +1>(a, Qb + al * S, aj, 1);
+        }
+        __syncthreads();
+        if (hb) {
+            cplx<T> u[R1];
+            stage_b_load<T, NN>(u, Qb + bl * S, bj, 1);
+            stage_b<T, NN, +1>(u, w);
+            stage_b_store<T, NN>(u, Qb + bl * S, bj, 1);
+        }
+        __syncthreads();
+        // inverse along m1 (lines n3, elements m1 at stride S): Q -> P, stage B to memory
+        if (ha) {
+            cplx<T> a[R0];
+            stage_a_load<T, NN>(a, Qb + al, aj, S);
+            stage_a_store<T, NN, +1>(a, Pb + al, aj, S);
+        }
+        __syncthreads();
+        if (hb) {
+            cplx<T> u[R1];
+            stage_b_load<T, NN>(u, Pb + bl, bj, S);
+            stage_b<T, NN, +1>(u, w);
+            cplx<T>* dst = X + (size_t)slot * B.ng + (size_t)m2i * NN + bl;
+#pragma unroll
+            for (int r = 0; r < R1; ++r) dst[(size_t)(bj + r * R0) * rs] = u[r];
+        }
+        cplx<T>* t = Pb;
+        Pb = Qb;
+        Qb = t;
+    }
+    if (B.parseval || deriv_only) {
+        constexpr int P2 = NT & (NT - 1) ? (NT >= 256 ? 256 : 128) : NT;   // power of two <= NT
+        static_assert(P2 <= NT && 2 * P2 >= NT, "reduction fold");
+        __syncthreads();
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < NT - P2) red[tid] += red[tid + P2];
+        __syncthreads();
+        for (int h = P2 / 2; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) parts[blockIdx.x] = red[0];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pass 3
 // ---------------------------------------------------------------------------
@@ -563,6 +731,16 @@ inline int specialised(const PairBatch& B) {
         default: { constexpr int NN = 0; CALL; } break;  \
     }
 
+template <typename T, int NN>
+void launch_pass2s(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only, unsigned grid,
+                   hipStream_t s) {
+    if constexpr (NN > 0) {
+        using C = P2S<NN>;
+        const size_t lds = sizeof(double) * C::NT + 2 * sizeof(cplx<T>) * NN * C::S;
+        hipLaunchKernelGGL((pass2s_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, X, tw, parts, deriv_only);
+    }
+}
+
 }  // namespace
 
 int pair_groups(const PairBatch& B) {
@@ -597,6 +775,10 @@ hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, doubl
     if constexpr (std::is_same_v<T, float>)
         if (B.regfft & REGFFT_PASS2) return launch_pass2_reg(B, X, parts, deriv_only, s);
     const unsigned grid = (unsigned)((size_t)B.N2 * pair_groups(B));
+    if (const int nnv = specialised(B)) {
+        OCCRIK_DISPATCH(nnv, (launch_pass2s<T, NN>(B, X, tw, parts, deriv_only, grid, s)));
+        return hipGetLastError();
+    }
     const size_t lds = lds_plane_bytes<T>(B.N1, B.N3) + sizeof(double) * kFftThreads;
     OCCRIK_DISPATCH(specialised(B), hipLaunchKernelGGL((pass2_kernel<T, NN>), dim3(grid), dim3(kFftThreads), lds, s,
                                                        B, X, tw, parts, deriv_only));
