@@ -76,12 +76,18 @@ def pass_kernel_names(info, precision):
     g = tuple(info.grid)
     n = g[0] if g[0] == g[1] == g[2] and g[0] in SPECIALISED else 0
     reg = int(info.reg_fft_passes)
-    jc = 8 if info.nocc <= 8 else 16
+    nout = info.nocc + info.nvir
+    jc = 8 if nout <= 8 else 16
     p1 = f"pass1r_kernel<{t}, {n}>" if reg & 1 else f"pass1_kernel<{t}, {n}>"
-    p2 = f"pass2r_kernel<{n}>" if reg & 2 else f"pass2_kernel<{t}, {n}>"
+    if reg & 2:
+        p2 = f"pass2r_kernel<{n}>"
+    else:
+        p2 = f"pass2s_kernel<{t}, {n}>" if n else f"pass2_kernel<{t}, 0>"
     if reg & 4:
         p3 = f"pass3r_kernel<{t}, {n}, 8>"
-    elif n and info.nocc <= 16:
+    elif n and t == "float" and nout <= 8:
+        p3 = f"pass3s_kernel<{t}, {n}>"
+    elif n and nout <= 16:
         p3 = f"pass3f_kernel<{t}, {n}, {jc}>"
     else:
         p3 = f"pass3_kernel<{t}, 0>"

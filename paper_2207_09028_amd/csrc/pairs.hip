@@ -682,6 +682,156 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     }
 }
 
+// Pass 3 for the compiled cubic sizes with at most 8 output orbitals: the column
+// block transform along m2 as two-stage lines, stage A fed from the prefetched
+// registers and stage B kept in registers, where the a-side sum (and the b-side
+// product) is formed; two LDS buffers alternate between summed pairs.  Per pair:
+// one barrier (two with the b-side sum) and 2 LDS accesses per point, against
+// six barriers and 6 accesses in pass3f_kernel.  Used for complex64.
+template <typename T, int NN>
+struct P3S {
+    static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
+    static constexpr int WB = colblock(NN, (int)sizeof(cplx<T>));
+    static constexpr int LN = 8 * WB;                   // lines (j, column) of the tile
+    static constexpr int LNP = pow2_at_least(LN);       // padded line count (tile row)
+    static constexpr int NA = LNP * R1, NBI = LNP * R0;
+    static constexpr int NT = ((NA > NBI ? NA : NBI) + 63) / 64 * 64;
+};
+
+template <typename T, int NN>
+__global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, const cplx<T>* __restrict__ X,
+                                                                cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
+                                                                const cplx<T>* __restrict__ twg) {
+    using C = P3S<T, NN>;
+    constexpr int R0 = C::R0, R1 = C::R1, WB = C::WB, LN = C::LN, LNP = C::LNP, NT = C::NT;
+    constexpr int NCB = NN / WB;
+    constexpr int PLANE = NN * NN;
+    constexpr int BP = NN * WB;                         // points of one column block
+    constexpr int BPT = (BP + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf1 = buf0 + NN * LNP;
+    const int n1 = blockIdx.x % NN;
+    const int cb = (blockIdx.x / NN) % NCB;
+    const int s = blockIdx.x / (NN * NCB);
+    const int c0 = cb * WB;
+    const int nocc = B.nocc, nout = B.nout;
+    const int nn = nocc * nout;
+    const int total = B.nb * nocc;
+    const int chunk = (total + B.splits - 1) / B.splits;
+    const int q0 = s * chunk;
+    const int q1 = min(total, q0 + chunk);
+    const int first_full = B.b0 + (B.diag ? 1 : 0);
+    const int full_base = B.diag ? B.ntri : 0;
+    const int tid = threadIdx.x;
+    const int line = tid % LNP;                         // (orbital jl, column w) of both stages
+    const int sj = tid / LNP;                           // stage A index (< R1) or stage B index (< R0)
+    const bool ha = tid < C::NA, hb = tid < C::NBI;
+    const int jl = line / WB;
+    const int w = line - jl * WB;
+    const bool active = line < LN && jl < nout;
+    const size_t plane_off = (size_t)n1 * PLANE + c0 + w;
+    auto slot_of = [&](int q, bool& cj) {
+        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        cj = false;
+        if (B.diag && bb == B.a) {
+            cj = jl < i;
+            return cj ? tri_index(jl, i, nocc) : tri_index(i, jl, nocc);
+        }
+        return full_base + (bb - first_full) * nn + i * nout + jl;
+    };
+    // stage A inputs: rows m2 = sj + r R1 of this line
+    cplx<T> xn[R0];
+    auto load_column = [&](int q) {
+        bool cj;
+        const cplx<T>* src = X + (size_t)(active ? slot_of(q, cj) : 0) * B.ng + plane_off;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? src[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
+    };
+    // stage B rows n2 = sj + r R0: twiddles, the a-side partner orbital (held) and the sums
+    const bool bact = hb && active;
+    cplx<T> tw[R1 - 1], pa[R1], acc[R1];
+    const cplx<T>* pa_src = static_cast<const cplx<T>*>(B.outp) + (size_t)(active ? jl : 0) * B.ng + plane_off;
+    if (hb) stage_b_twiddles<T, NN>(tw, twg + kMaxN, sj);
+    else {
+#pragma unroll
+        for (int r = 0; r < R1 - 1; ++r) tw[r] = mk<T>(T(0), T(0));
+    }
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+        pa[r] = bact && B.reuse ? pa_src[(size_t)(sj + r * R0) * NN] : mk<T>(T(0), T(0));
+        acc[r] = mk<T>(T(0), T(0));
+    }
+    if (q0 < q1) load_column(q0);
+    cplx<T>* Pb = buf0;
+    cplx<T>* Qb = buf1;
+    for (int q = q0; q < q1; ++q) {
+        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        const bool bside = B.reuse && !(B.diag && bb == B.a);
+        bool cj;
+        (void)slot_of(q, cj);
+        if (ha) {
+            cplx<T> a[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) a[r] = xn[r];
+            stage_a_store<T, NN, +1>(a, Pb + line, sj, LNP);
+        }
+        // in flight during this pair's transform: the next pair's column, this pair's
+        // summed orbital and its W block
+        if (q + 1 < q1) load_column(q + 1);
+        const cplx<T>* ui_src = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
+        cplx<T> ui[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) ui[r] = bact ? ui_src[(size_t)(sj + r * R0) * NN] : mk<T>(T(0), T(0));
+        cplx<T>* wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
+        cplx<T> wv[BPT];
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int e = tid + t * NT;
+            const int n2 = e / WB, ww = e - n2 * WB;
+            wv[t] = bside && e < BP ? wout[(size_t)n2 * NN + ww] : mk<T>(T(0), T(0));
+        }
+        __syncthreads();
+        if (hb) {
+            cplx<T> y[R1];
+            stage_b_load<T, NN>(y, Pb + line, sj, LNP);
+            stage_b<T, NN, +1>(y, tw);
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < R1; ++r) {
+                    cplx<T> v = y[r];
+                    if (cj) v.y = -v.y;
+                    acc[r] = mk<T>(acc[r].x + ui[r].x * v.x - ui[r].y * v.y, acc[r].y + ui[r].x * v.y + ui[r].y * v.x);
+                    // b-side product o conj(v), in this item's own rows of the buffer
+                    if (bside) Pb[(sj + r * R0) * LNP + line] = mk<T>(pa[r].x * v.x + pa[r].y * v.y,
+                                                                     pa[r].y * v.x - pa[r].x * v.y);
+                }
+            }
+        }
+        if (bside) {
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < BPT; ++t) {
+                const int e = tid + t * NT;
+                if (e < BP) {
+                    const int n2 = e / WB, ww = e - n2 * WB;
+                    cplx<T> sum = wv[t];
+                    for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, Pb[n2 * LNP + j * WB + ww]);
+                    wout[(size_t)n2 * NN + ww] = sum;
+                }
+            }
+        }
+        cplx<T>* t = Pb;
+        Pb = Qb;
+        Qb = t;
+    }
+    if (bact) {
+        cplx<T>* out = Wpart + ((size_t)s * nout + jl) * B.ng + plane_off;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) out[(size_t)(sj + r * R0) * NN] = acc[r];
+    }
+}
+
 template <typename T>
 __global__ void wreduce_kernel(PairBatch B, const cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W) {
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -738,6 +888,17 @@ void launch_pass2s(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* pa
         using C = P2S<NN>;
         const size_t lds = sizeof(double) * C::NT + 2 * sizeof(cplx<T>) * NN * C::S;
         hipLaunchKernelGGL((pass2s_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, X, tw, parts, deriv_only);
+    }
+}
+
+template <typename T, int NN>
+void launch_pass3s(const PairBatch& B, const cplx<T>* X, cplx<T>* Wpart, cplx<T>* W, const cplx<T>* tw,
+                   hipStream_t s) {
+    if constexpr (NN > 0) {
+        using C = P3S<T, NN>;
+        const unsigned grid = (unsigned)((size_t)NN * (NN / C::WB) * B.splits);
+        const size_t lds = 2 * sizeof(cplx<T>) * NN * C::LNP;
+        hipLaunchKernelGGL((pass3s_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, X, Wpart, W, tw);
     }
 }
 
@@ -798,6 +959,14 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
     if constexpr (std::is_same_v<T, float>)
         if ((B.regfft & REGFFT_PASS3) && B.nout <= 8) return launch_pass3_reg(B, X, psi, Wpart, W, s);
     const int nnv = specialised(B);
+    // complex64 only: the complex128 form needs ~200 VGPRs and half the resident waves,
+    // which made it slower than pass3f_kernel
+    if constexpr (std::is_same_v<T, float>) {
+        if (nnv > 0 && B.nout <= 8) {
+            OCCRIK_DISPATCH(nnv, (launch_pass3s<T, NN>(B, X, Wpart, W, tw, s)));
+            return hipGetLastError();
+        }
+    }
     if (nnv > 0 && B.nout <= 16) {
         const int wb = colblock(nnv, (int)sizeof(cplx<T>));
         const unsigned grid = (unsigned)((size_t)nnv * (nnv / wb) * B.splits);
