@@ -165,6 +165,8 @@ typedef struct {
                                      from the nocc occupied columns, K_{mu p} and K~ cover all
                                      columns (K~ C_p equals the conventional K C_p for every
                                      column), E_x is the occupied trace.  0 = ground state. */
+    int32_t contract_chunks;      /* grid chunks of the contraction's FP64 partial sums, 1..64;
+                                     0 = chosen by the plan (N_g / 4096, clamped) */
 } occrik_params;
 
 typedef struct occrik_plan occrik_plan;
@@ -182,6 +184,8 @@ typedef struct {
     int32_t colloc_chunk;         /* grid points per collocation chunk */
     int32_t reg_fft_passes;       /* bit p-1 set: pair pass p runs register-resident transforms */
     int32_t nvir;                 /* conduction bands treated exactly */
+    int32_t contract_chunks;      /* grid chunks of the contraction */
+    int32_t tuned;                /* 1 after occrik_plan_autotune */
 } occrik_plan_info;
 
 /* Per-phase device timings of the last build(s), from HIP events recorded on
@@ -236,6 +240,34 @@ occrik_status occrik_build(occrik_plan *plan, const double *C, double *K, double
  * reported by occrik_plan_status after the stream reaches them.  If dK is
  * non-NULL and a Cholesky fails, the K~ block of that k is left zeroed. */
 occrik_status occrik_build_device(occrik_plan *plan, const void *dC, void *dK, void *dKmi, double *dEx);
+
+/* Autotuner (not part of the paper): times whole builds of C on the plan's stream
+ * over the settings the plan's parameters leave open and keeps the fastest, by
+ * coordinate descent in this order:
+ *   k batch          (FFT batch: summed k-points per pair-pass launch) the plan's
+ *                    allocated batch, a half and a quarter of it; fixed when
+ *                    params.kbatch > 0
+ *   pair transforms  LDS two-stage passes or register-resident passes; complex64
+ *                    plans with a register-supported grid, no conduction bands and
+ *                    neither OCCRIK_FLAG_LDS_FFT nor OCCRIK_FLAG_REG_FFT_ALL set
+ *   contraction      grid chunks of the MFMA contraction (its tiles over the grid):
+ *                    the plan's count, twice and half of it, within 1..64; fixed for
+ *                    integral-direct plans and when params.contract_chunks > 0
+ * One untimed build comes first.  Results of later builds depend on the chosen
+ * settings only at rounding level (summation order); a plan created with
+ * params.kbatch, the FFT flag and params.contract_chunks set to the chosen values
+ * builds bitwise the same.  dC as in occrik_build_device (device memory);
+ * synchronous; the tuning builds' outputs are discarded (occrik_grad needs a new
+ * build).  out may be NULL. */
+typedef struct {
+    int32_t kbatch;               /* chosen k batch */
+    int32_t reg_fft;              /* 1: register-resident pair passes chosen */
+    int32_t contract_chunks;      /* chosen contraction chunks */
+    int32_t builds;               /* timed builds */
+    double ms_initial;            /* build time with the settings before tuning */
+    double ms_best;               /* build time with the chosen settings */
+} occrik_tune_info;
+occrik_status occrik_plan_autotune(occrik_plan *plan, const void *dC, occrik_tune_info *out);
 
 /* Conventional GPW exchange on the plan's cell, grid, kernel and precision: the
  * algorithms occ-RI-K is measured against, giving the full AO x AO exchange matrix

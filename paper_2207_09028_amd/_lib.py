@@ -46,7 +46,8 @@ class Basis(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("kmesh", c_int32 * 3), ("grid", c_int32 * 3), ("nocc", c_int32), ("kernel", c_int32),
                 ("omega", c_double), ("nyquist", c_int32), ("precision", c_int32), ("lattice_tol", c_double),
-                ("kbatch", c_int32), ("flags", c_int32), ("mem_budget", c_size_t), ("nvir", c_int32)]
+                ("kbatch", c_int32), ("flags", c_int32), ("mem_budget", c_size_t), ("nvir", c_int32),
+                ("contract_chunks", c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -57,7 +58,12 @@ class PlanInfo(ctypes.Structure):
                 ("bytes_chi", c_size_t), ("bytes_workspace", c_size_t),
                 ("pair_transforms", ctypes.c_int64), ("plan_seconds", c_double),
                 ("integral_direct", c_int32), ("colloc_chunk", c_int32), ("reg_fft_passes", c_int32),
-                ("nvir", c_int32)]
+                ("nvir", c_int32), ("contract_chunks", c_int32), ("tuned", c_int32)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("kbatch", c_int32), ("reg_fft", c_int32), ("contract_chunks", c_int32), ("builds", c_int32),
+                ("ms_initial", c_double), ("ms_best", c_double)]
 
 
 class Profile(ctypes.Structure):
@@ -78,6 +84,7 @@ SIGNATURES = {
     "occrik_build": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
     "occrik_build_device": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
     "occrik_conventional_k": (c_int32, [PlanP, c_int32, c_void_p, c_void_p, c_void_p]),
+    "occrik_plan_autotune": (c_int32, [PlanP, c_void_p, ctypes.POINTER(TuneInfo)]),
     "occrik_plan_status": (c_int32, [PlanP]),
     "occrik_last_error_k": (c_int32, [PlanP]),
     "occrik_grad": (c_int32, [PlanP, c_double, c_void_p, ctypes.POINTER(c_double)]),

@@ -59,6 +59,8 @@ struct DeviceGuard {
 // output AOs of k_a per group of the conventional pair passes (the occ-RI-K pass-3
 // tile of eight output orbitals, with the next pair prefetched)
 constexpr int kConvGroup = 8;
+// largest number of grid chunks of the contraction's partial sums
+constexpr int kMaxContractChunks = 64;
 
 struct ProfileEvents {
     hipEvent_t e[5];
@@ -83,6 +85,9 @@ struct occrik_plan {
     bool fp64 = true;
     size_t elem = 16;
     int kbatch = 1, splits = 1, nchunks = 1, group = 8;
+    int kbatch_max = 1;        // k batch the pair workspaces were sized for
+    int kpart_chunks = 1;      // contraction chunks the partial-sum buffer holds
+    bool tuned = false;        // occrik_plan_autotune has chosen kbatch / regfft / nchunks
 
     // device memory
     std::vector<void*> allocations;
@@ -785,6 +790,8 @@ occrik_status validate(const occrik_cell* cell, const occrik_basis* basis, const
     if ((pr->flags & OCCRIK_FLAG_LDS_FFT) && (pr->flags & OCCRIK_FLAG_REG_FFT_ALL))
         return fail(OCCRIK_ERR_INVALID_ARG, "OCCRIK_FLAG_LDS_FFT and OCCRIK_FLAG_REG_FFT_ALL exclude each other");
     if (pr->kbatch < 0) return fail(OCCRIK_ERR_INVALID_ARG, "kbatch must be >= 0");
+    if (pr->contract_chunks < 0 || pr->contract_chunks > kMaxContractChunks)
+        return fail(OCCRIK_ERR_INVALID_ARG, "contract_chunks must be 0..64");
     return OCCRIK_OK;
 }
 
@@ -887,9 +894,10 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
         const size_t cap = (size_t)16 << 30;
         P->kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_k));
     }
+    P->kbatch_max = P->kbatch;
     P->splits = splits_for(P, P->kbatch);
     P->group = nout;
-    P->nchunks = std::max(1, std::min(64, ng / 4096));
+    P->nchunks = params->contract_chunks > 0 ? params->contract_chunks : std::max(1, std::min(64, ng / 4096));
     const size_t max_groups = (size_t)P->kbatch * ((nocc * nout + P->group - 1) / P->group) +
                               (nocc * (nocc + 1) / 2 + P->group - 1) / P->group;
 
@@ -940,6 +948,7 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
     A(&P->kvals, P->elem / 2 * (size_t)P->kbatch * ng);
     A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nout * P->nchunks);
+    P->kpart_chunks = P->nchunks;
     A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nout);
     A((void**)&P->Kij, sizeof(double2) * (size_t)nk * nout * nout);
     A((void**)&P->L, sizeof(double2) * (size_t)nk * nout * nout);
@@ -1005,6 +1014,8 @@ occrik_status occrik_plan_query(const occrik_plan* P, occrik_plan_info* info) {
                                       (int64_t)P->nk * P->nocc * (P->nocc + 1) / 2
                                 : (int64_t)P->nk * P->nk * P->nocc * P->nout;
     info->plan_seconds = P->plan_seconds;
+    info->contract_chunks = P->nchunks;
+    info->tuned = P->tuned ? 1 : 0;
     return OCCRIK_OK;
 }
 
@@ -1027,6 +1038,116 @@ occrik_status occrik_build_device(occrik_plan* P, const void* dC, void* dK, void
     P->last_err_k = -1;
     return P->fp64 ? build_impl<double>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx)
                    : build_impl<float>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx);
+}
+
+occrik_status occrik_plan_autotune(occrik_plan* P, const void* dC, occrik_tune_info* out) {
+    if (!P || !dC) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C");
+    DeviceGuard guard(P->device);
+    hipStream_t s = P->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    OCCRIK_HIP(hipEventCreate(&e0));
+    OCCRIK_HIP(hipEventCreate(&e1));
+    const int saved_profiling = P->profiling;
+    P->profiling = 0;
+    int builds = 0;
+    auto timed = [&](double& ms) -> occrik_status {
+        occrik_status st = OCCRIK_OK;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(OCCRIK_ERR_DEVICE, "autotune event");
+        st = P->fp64 ? build_impl<double>(P, (const double2*)dC, nullptr, nullptr, nullptr)
+                     : build_impl<float>(P, (const double2*)dC, nullptr, nullptr, nullptr);
+        if (st != OCCRIK_OK) return st;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(OCCRIK_ERR_DEVICE, "autotune event");
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fail(OCCRIK_ERR_DEVICE, "autotune timing");
+        ms = f;
+        ++builds;
+        return OCCRIK_OK;
+    };
+    auto set_reg = [&](bool on) {
+        P->params.flags &= ~OCCRIK_FLAG_REG_FFT_ALL;
+        if (on) P->params.flags |= OCCRIK_FLAG_REG_FFT_ALL;
+    };
+    // contraction chunks above the allocated count need a larger partial-sum buffer;
+    // a candidate that does not fit (device memory or mem_budget) is skipped
+    auto ensure_chunks = [&](int nc) -> bool {
+        if (nc <= P->kpart_chunks) return true;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        double2* bigger = nullptr;
+        if (P->alloc((void**)&bigger, sizeof(double2) * (size_t)P->nk * P->nao * P->nout * nc) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        P->release(P->Kpart);
+        P->Kpart = bigger;
+        P->kpart_chunks = nc;
+        return true;
+    };
+    occrik_status st = OCCRIK_OK;
+    double ms = 0.0, best = 0.0, initial = 0.0;
+    const bool reg_open = P->regfft && !(P->params.flags & (OCCRIK_FLAG_LDS_FFT | OCCRIK_FLAG_REG_FFT_ALL));
+    const bool reg_initial = (P->params.flags & OCCRIK_FLAG_REG_FFT_ALL) != 0;
+    do {
+        if ((st = timed(ms)) != OCCRIK_OK) break;   // untimed warm-up
+        if ((st = timed(initial)) != OCCRIK_OK) break;
+        best = initial;
+        // k batch: the allocated one, a half, a quarter
+        if (P->params.kbatch == 0) {
+            const int k0 = P->kbatch_max;
+            int chosen = P->kbatch;
+            for (int div : {2, 4}) {
+                const int kb = (k0 + div - 1) / div;
+                if (kb < 1 || kb == chosen || kb == k0) continue;
+                P->kbatch = kb;
+                if ((st = timed(ms)) != OCCRIK_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    chosen = kb;
+                }
+            }
+            if (st != OCCRIK_OK) break;
+            P->kbatch = chosen;
+        }
+        // pair transforms: LDS two-stage or register-resident
+        if (reg_open) {
+            set_reg(!reg_initial);
+            if ((st = timed(ms)) != OCCRIK_OK) break;
+            if (ms < best) best = ms;
+            else set_reg(reg_initial);
+        }
+        // contraction chunks
+        if (!P->direct && P->params.contract_chunks == 0) {
+            const int n0 = P->nchunks;
+            int chosen = n0;
+            for (int nc : {std::min(kMaxContractChunks, 2 * n0), std::max(1, n0 / 2)}) {
+                if (nc == n0 || nc == chosen || !ensure_chunks(nc)) continue;
+                P->nchunks = nc;
+                if ((st = timed(ms)) != OCCRIK_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    chosen = nc;
+                }
+            }
+            if (st != OCCRIK_OK) break;
+            P->nchunks = chosen;
+        }
+    } while (false);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->profiling = saved_profiling;
+    P->built = false;
+    if (st != OCCRIK_OK) return st;
+    P->tuned = true;
+    if (out) {
+        out->kbatch = P->kbatch;
+        out->reg_fft = (P->params.flags & OCCRIK_FLAG_REG_FFT_ALL) ? 1 : 0;
+        out->contract_chunks = P->nchunks;
+        out->builds = builds;
+        out->ms_initial = initial;
+        out->ms_best = best;
+    }
+    return OCCRIK_OK;
 }
 
 occrik_status occrik_conventional_k(occrik_plan* P, int32_t algo, const void* dC, void* dK, double* dEx) {

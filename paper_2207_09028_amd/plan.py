@@ -43,6 +43,7 @@ class PlanSpec:
     mem_budget: int = 0
     flags: int = 0
     nvir: int = 0
+    contract_chunks: int = 0
 
     @classmethod
     def from_problem(cls, prob, **overrides):
@@ -80,7 +81,7 @@ class Plan:
         params = _lib.Params((ctypes.c_int32 * 3)(*spec.kmesh), (ctypes.c_int32 * 3)(*spec.grid), int(spec.nocc),
                              int(spec.kernel), float(spec.omega), int(spec.nyquist), int(spec.precision),
                              float(spec.lattice_tol), int(spec.kbatch), int(spec.flags), int(spec.mem_budget),
-                             int(spec.nvir))
+                             int(spec.nvir), int(spec.contract_chunks))
         handle = _lib.PlanP()
         with torch.cuda.device(self.device):
             st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params),
@@ -155,6 +156,18 @@ class Plan:
         self.build_device(C, K, Kmi, Ex)
         self.status()
         return dict(K=K, Kmi=Kmi, Ex=Ex)
+
+    def autotune(self, C):
+        """occrik_plan_autotune: time builds of C over the open settings (k batch, pair
+        transform form, contraction chunks) and keep the fastest; returns a dict of the
+        choice and the timings.  Synchronous."""
+        self._check_C(C)
+        self._sync_stream()
+        ti = _lib.TuneInfo()
+        check(self._lib.occrik_plan_autotune(self._h, ctypes.c_void_p(C.data_ptr()), ctypes.byref(ti)), self._h)
+        self.info = self.query()
+        return dict(kbatch=ti.kbatch, reg_fft=ti.reg_fft, contract_chunks=ti.contract_chunks, builds=ti.builds,
+                    ms_initial=ti.ms_initial, ms_best=ti.ms_best)
 
     def conventional_k(self, C, algo="mo", K=None, Ex=None):
         """occrik_conventional_k: the full AO x AO exchange matrix by MO-RI-K (Alg. 2,

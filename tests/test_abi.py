@@ -56,11 +56,11 @@ def _create(**override):
                        sl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        se.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     p = dict(kmesh=(1, 1, 1), grid=(8, 8, 8), nocc=1, kernel=0, omega=0.0, nyquist=1, precision=0,
-             lattice_tol=1e-12, kbatch=0, flags=0, mem_budget=0, nvir=0)
+             lattice_tol=1e-12, kbatch=0, flags=0, mem_budget=0, nvir=0, contract_chunks=0)
     p.update(override)
     params = _lib.Params((ctypes.c_int32 * 3)(*p["kmesh"]), (ctypes.c_int32 * 3)(*p["grid"]), p["nocc"],
                          p["kernel"], p["omega"], p["nyquist"], p["precision"], p["lattice_tol"], p["kbatch"],
-                         p["flags"], p["mem_budget"], p["nvir"])
+                         p["flags"], p["mem_budget"], p["nvir"], p["contract_chunks"])
     h = _lib.PlanP()
     st = lib.occrik_plan_create(ctypes.byref(cell), ctypes.byref(basis), ctypes.byref(params), 0, None,
                                 ctypes.byref(h))
@@ -72,6 +72,8 @@ def _create(**override):
     (dict(grid=(8, 8, 96)), 2),         # beyond the largest supported extent
     (dict(l=4), 2),                     # g functions are not supported
     (dict(nocc=0), 1),
+    (dict(contract_chunks=-1), 1),
+    (dict(contract_chunks=65), 1),
     (dict(nocc=17), 1),
     (dict(nvir=-1), 1),
     (dict(nocc=10, nvir=7), 1),         # nocc + nvir above 16
@@ -98,5 +100,7 @@ def test_null_arguments_are_rejected():
     assert lib.occrik_build(None, None, None, None, None) == 1
     assert lib.occrik_build_device(None, None, None, None, None) == 1
     assert lib.occrik_grad(None, 1.0, None, None) == 1
+    assert lib.occrik_plan_autotune(None, None, None) == 1
+    assert lib.occrik_conventional_k(None, 2, None, None, None) == 1
     assert lib.occrik_last_error_k(None) == -1
     lib.occrik_plan_destroy(None)

@@ -342,3 +342,53 @@ def test_conduction_bands_leave_energy_and_omega_derivative_unchanged():
     _, d_occ = occ.grad(1.0, want_C=False, want_omega=True)
     _, d_ext = ext.grad(1.0, want_C=False, want_omega=True)
     assert abs(d_occ - d_ext) < 1e-11 * abs(d_occ)
+
+
+# ----------------------------------------------------------------------------
+# autotuner: k batch, pair-transform form and contraction chunks chosen by timing
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,grid", [(pkg.PREC_FP64, (24, 24, 24)), (pkg.PREC_FP32, (24, 24, 24)),
+                                            (pkg.PREC_FP32_SPLIT, (12, 10, 9))])
+def test_autotuned_plan_builds_bitwise_as_the_explicit_settings(precision, grid):
+    prob = W.small_problem(kmesh=(2, 2, 2), grid=grid, nocc=4, counts=(2, 1, 1), seed=31)
+    C = W.random_coefficients(prob)
+    Ct = torch.from_numpy(C).to("cuda")
+    plan = Plan(PlanSpec.from_problem(prob, precision=precision))
+    before = plan.query()
+    res = plan.autotune(Ct)
+    info = plan.query()
+    assert info.tuned == 1 and res["builds"] >= 2
+    assert info.kbatch == res["kbatch"] and info.contract_chunks == res["contract_chunks"]
+    assert 1 <= res["kbatch"] <= before.kbatch and 1 <= res["contract_chunks"] <= 64
+    assert res["ms_best"] <= res["ms_initial"]
+    if res["reg_fft"]:
+        assert precision != pkg.PREC_FP64
+    out = plan.build(Ct)
+    flags = pkg.FLAG_REG_FFT_ALL if res["reg_fft"] else pkg.FLAG_LDS_FFT
+    ref = Plan(PlanSpec.from_problem(prob, precision=precision, kbatch=res["kbatch"], flags=flags,
+                                     contract_chunks=res["contract_chunks"])).build(Ct)
+    for key in ("K", "Kmi", "Ex"):
+        assert torch.equal(out[key], ref[key]), key
+    if precision == pkg.PREC_FP64:
+        chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+        oref = occrik.build(prob, C, chi=chi, nyquist="symmetric")
+        assert abs(float(out["Ex"][0]) - oref["Ex"]) < 1e-10 * abs(oref["Ex"])
+
+
+def test_autotune_keeps_the_settings_the_parameters_fix():
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=3, counts=(2, 1, 1), seed=32)
+    Ct = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+    plan = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP32, kbatch=1, flags=pkg.FLAG_LDS_FFT,
+                                      contract_chunks=3))
+    res = plan.autotune(Ct)
+    assert (res["kbatch"], res["reg_fft"], res["contract_chunks"]) == (1, 0, 3)
+    direct = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP32, flags=pkg.FLAG_DIRECT))
+    n0 = direct.query().contract_chunks
+    res = direct.autotune(Ct)
+    assert res["contract_chunks"] == n0
+    # a tuned integral-direct plan still equals its stored counterpart bitwise
+    stored = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP32, kbatch=res["kbatch"],
+                                        flags=pkg.FLAG_REG_FFT_ALL if res["reg_fft"] else pkg.FLAG_LDS_FFT))
+    a, b = direct.build(Ct), stored.build(Ct)
+    assert torch.equal(a["Kmi"], b["Kmi"]) and torch.equal(a["Ex"], b["Ex"])
