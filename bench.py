@@ -78,7 +78,10 @@ def pass_kernel_names(info, precision):
     reg = int(info.reg_fft_passes)
     nout = info.nocc + info.nvir
     jc = 8 if nout <= 8 else 16
-    p1 = f"pass1r_kernel<{t}, {n}>" if reg & 1 else f"pass1_kernel<{t}, {n}>"
+    if reg & 1:
+        p1 = f"pass1r_kernel<{t}, {n}>"
+    else:
+        p1 = f"pass1g_kernel<{t}, {n}>" if n else f"pass1_kernel<{t}, 0>"
     if reg & 2:
         p2 = f"pass2r_kernel<{n}>"
     else:

@@ -78,6 +78,111 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
     }
 }
 
+// Pass 1 for the compiled cubic sizes, one workgroup per x-plane and row of stored
+// pairs (one summed orbital i of block b with all its partners j): psi~_{i b} on
+// the plane is held in registers for the whole row and the next partner's plane is
+// loaded while the current pair is transformed.  The plane transform runs as
+// two-stage lines: stage A of axis n2 on the pair density in registers (lanes
+// along n3), stage B in place, axis n3 from one LDS buffer into a second, and a
+// coalesced copy out of the second.  4 barriers and 8 LDS accesses per point per pair.
+template <int NN>
+struct P1G {
+    static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
+    static constexpr int NA = NN * R1, NBI = NN * R0;
+    static constexpr int NT = ((NA > NBI ? NA : NBI) + 63) / 64 * 64;
+    static constexpr int S = NN + 1;
+};
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi,
+                                                             cplx<T>* __restrict__ X,
+                                                             const cplx<T>* __restrict__ twg) {
+    using C = P1G<NN>;
+    constexpr int R0 = C::R0, R1 = C::R1, S = C::S, NT = C::NT;
+    constexpr int PLANE = NN * NN;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* Qb = Pb + NN * S;
+    const int n1 = blockIdx.x % NN;
+    const int row = blockIdx.x / NN;
+    // row -> (block b, summed orbital i, first slot, first partner j0); the diagonal
+    // block (if any) comes first and stores the partners j >= i of row i
+    const int nocc = B.nocc, nout = B.nout;
+    int b, i, slot0, j0;
+    if (B.diag && row < nocc) {
+        b = B.a;
+        i = row;
+        j0 = i;
+        slot0 = tri_index(i, i, nocc);
+    } else {
+        const int r = row - (B.diag ? nocc : 0);
+        const int blk = r / nocc;
+        i = r - blk * nocc;
+        b = B.b0 + (B.diag ? 1 : 0) + blk;
+        j0 = 0;
+        slot0 = (B.diag ? B.ntri : 0) + blk * nocc * nout + i * nout;
+    }
+    const int tid = threadIdx.x;
+    const bool ha = tid < C::NA, hb = tid < C::NBI;
+    const int sj = tid / NN, ln = tid - sj * NN;
+    cplx<T> w[R1 - 1];
+    if (hb) stage_b_twiddles<T, NN>(w, twg + kMaxN, sj);
+    else {
+#pragma unroll
+        for (int r = 0; r < R1 - 1; ++r) w[r] = mk<T>(T(0), T(0));
+    }
+    // this thread's stage A points (n2 = sj + r R1, n3 = ln) of psi~_{i b}, held
+    const size_t poff = (size_t)n1 * PLANE + ln;
+    const cplx<T>* pi = psi + ((size_t)b * B.kstride + i) * B.ng + poff;
+    cplx<T> ui[R0], xn[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) ui[r] = ha ? pi[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
+    auto load_partner = [&](int j) {
+        const cplx<T>* pj = static_cast<const cplx<T>*>(B.outp) + (size_t)j * B.ng + poff;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) xn[r] = ha ? pj[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
+    };
+    load_partner(j0);
+    for (int j = j0; j < nout; ++j) {
+        const int slot = slot0 + (j - j0);
+        // axis n2 (lines n3 = ln, elements n2 at stride S): stage A on the pair density
+        if (ha) {
+            cplx<T> a[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) a[r] = cjmul<T>(ui[r], xn[r]);
+            stage_a_store<T, NN, -1>(a, Pb + ln, sj, S);
+        }
+        if (j + 1 < nout) load_partner(j + 1);
+        __syncthreads();
+        if (hb) {
+            cplx<T> u[R1];
+            stage_b_load<T, NN>(u, Pb + ln, sj, S);
+            stage_b<T, NN, -1>(u, w);
+            stage_b_store<T, NN>(u, Pb + ln, sj, S);
+        }
+        __syncthreads();
+        // axis n3 (lines m2 = ln at stride S, elements adjacent): P -> Q
+        if (ha) {
+            cplx<T> a[R0];
+            stage_a_load<T, NN>(a, Pb + ln * S, sj, 1);
+            stage_a_store<T, NN, -1>(a, Qb + ln * S, sj, 1);
+        }
+        __syncthreads();
+        if (hb) {
+            cplx<T> u[R1];
+            stage_b_load<T, NN>(u, Qb + ln * S, sj, 1);
+            stage_b<T, NN, -1>(u, w);
+            stage_b_store<T, NN>(u, Qb + ln * S, sj, 1);
+        }
+        __syncthreads();
+        cplx<T>* out = X + (size_t)slot * B.ng + (size_t)n1 * PLANE;
+        for (int e = tid; e < PLANE; e += NT) {
+            const int m2 = e / NN, m3 = e - m2 * NN;
+            out[e] = Qb[m2 * S + m3];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
@@ -882,6 +987,16 @@ inline int specialised(const PairBatch& B) {
     }
 
 template <typename T, int NN>
+void launch_pass1g(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, unsigned grid,
+                   hipStream_t s) {
+    if constexpr (NN > 0) {
+        using C = P1G<NN>;
+        const size_t lds = 2 * sizeof(cplx<T>) * NN * C::S;
+        hipLaunchKernelGGL((pass1g_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, psi, X, tw);
+    }
+}
+
+template <typename T, int NN>
 void launch_pass2s(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only, unsigned grid,
                    hipStream_t s) {
     if constexpr (NN > 0) {
@@ -915,6 +1030,11 @@ template <typename T>
 hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s) {
     if constexpr (std::is_same_v<T, float>)
         if (B.regfft & REGFFT_PASS1) return launch_pass1_reg(B, psi, X, s);
+    if (const int nnv = specialised(B)) {
+        const int rows = (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * B.nocc;
+        OCCRIK_DISPATCH(nnv, (launch_pass1g<T, NN>(B, psi, X, tw, (unsigned)((size_t)NN * rows), s)));
+        return hipGetLastError();
+    }
     const unsigned grid = (unsigned)((size_t)B.N1 * B.nslots);
     const size_t lds = lds_plane_bytes<T>(B.N2, B.N3);
     OCCRIK_DISPATCH(specialised(B),
