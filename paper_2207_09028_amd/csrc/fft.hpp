@@ -77,23 +77,24 @@ template <typename T, int DIR> struct Dft<T, 5, DIR> {
     }
 };
 
-// 6 = 3 x 2: inner 3-point DFTs over x[2 n1 + n2], twiddle w6^{n2 k1}, outer 2-point.
+// 6 = 2 x 3 with coprime factors (Good-Thomas prime-factor mapping, no twiddles):
+// input n = (3 n1 + 2 n2) mod 6, so w6^{n k} = w2^{n1 k} w3^{n2 k}; 2-point DFTs over
+// n1 for each n2, then 3-point DFTs over n2 for each k1 = k mod 2, and X_k is the
+// result at (k mod 2, k mod 3).
 template <typename T, int DIR> struct Dft<T, 6, DIR> {
     static __device__ __forceinline__ void run(cplx<T>* v) {
-        cplx<T> e[3] = {v[0], v[2], v[4]};
-        cplx<T> o[3] = {v[1], v[3], v[5]};
+        // n2 = 0, 1, 2 take the input pairs (n1 = 0, 1) = (0, 3), (2, 5), (4, 1)
+        cplx<T> e[3] = {cadd<T>(v[0], v[3]), cadd<T>(v[2], v[5]), cadd<T>(v[4], v[1])};   // k1 = 0
+        cplx<T> o[3] = {csub<T>(v[0], v[3]), csub<T>(v[2], v[5]), csub<T>(v[4], v[1])};   // k1 = 1
         Dft<T, 3, DIR>::run(e);
         Dft<T, 3, DIR>::run(o);
-        const T h = T(0.5), s = T(0.86602540378443864676372317075294);
-        // w6^1 = (1/2, DIR*s), w6^2 = (-1/2, DIR*s)
-        o[1] = cmul<T>(o[1], mk<T>(h, T(DIR) * s));
-        o[2] = cmul<T>(o[2], mk<T>(-h, T(DIR) * s));
-        v[0] = cadd<T>(e[0], o[0]);
-        v[3] = csub<T>(e[0], o[0]);
-        v[1] = cadd<T>(e[1], o[1]);
-        v[4] = csub<T>(e[1], o[1]);
-        v[2] = cadd<T>(e[2], o[2]);
-        v[5] = csub<T>(e[2], o[2]);
+        // k = 0..5 -> (k mod 2, k mod 3)
+        v[0] = e[0];
+        v[1] = o[1];
+        v[2] = e[2];
+        v[3] = o[0];
+        v[4] = e[1];
+        v[5] = o[2];
     }
 };
 
