@@ -12,7 +12,11 @@
         (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for
         the plain copy above; prints "key: value" lines that bench.py reads back
         (with the SHA-256 of the kernel's source, so a changed kernel reads as
-        unmeasured).
+        unmeasured);
+    python -m paper_2207_09028_amd.profiling phases <fetch.csv> <write.csv> \
+            <copy_fetch.csv> <copy_write.csv> <kernel_stats.csv>
+        the same measured bytes for every pair pass and contraction kernel, with
+        the achieved GB/s over the kernel trace's average duration.
 """
 from __future__ import annotations
 
@@ -86,6 +90,43 @@ def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, cfetch_csv
     print(f"hbm_bytes_per_launch: {total:.6e}")
 
 
+def phases(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str, stats_csv: str,
+           kernels=("pass1", "pass2", "pass3", "wreduce", "kvals", "orbitals_mfma", "contract_mfma"),
+           copy_gib: float = 2.0):
+    """Measured HBM bytes per dispatch (counters, copy-calibrated) and achieved GB/s over the
+    kernel-trace average duration, for every kernel whose name contains one of ``kernels``."""
+    import collections
+    import re
+    nbytes = int(copy_gib * (1 << 30)) // 4 * 4
+    fs = _copy_scale(cfetch_csv, "FETCH_SIZE", nbytes)
+    ws = _copy_scale(cwrite_csv, "WRITE_SIZE", nbytes)
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(lambda: [0.0, 0])
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                m = re.search(r"(\w+<[^()]*>)\(", r["Kernel_Name"])
+                k = m.group(1) if m else r["Kernel_Name"].split("(")[0]
+                acc[k][0] += float(r["Counter_Value"])
+                acc[k][1] += 1
+        return acc
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    rows = list(csv.DictReader(open(stats_csv)))
+    key_a = next(k for k in rows[0] if k.lower().startswith("averagens"))
+    avg = {}
+    for r in rows:
+        m = re.search(r"(\w+<[^()]*>)\(", r["Name"])
+        avg[m.group(1) if m else r["Name"].split("(")[0]] = float(r[key_a]) / 1e6
+    print(f"{'kernel':36s} {'disp':>5s} {'read GB':>9s} {'write GB':>9s} {'avg ms':>8s} {'GB/s':>8s}")
+    for k in sorted(fetch, key=lambda k: -(fetch[k][0] / max(fetch[k][1], 1))):
+        if not any(s in k for s in kernels) or k not in avg:
+            continue
+        f = fetch[k][0] / fetch[k][1] * 1024.0 * fs
+        w = write[k][0] / max(write[k][1], 1) * 1024.0 * ws
+        print(f"{k:36s} {fetch[k][1]:5d} {f / 1e9:9.3f} {w / 1e9:9.3f} {avg[k]:8.3f} {(f + w) / (avg[k] * 1e6):8.1f}")
+
+
 def read_traffic(path: str) -> dict:
     out = {}
     for line in open(path):
@@ -108,11 +149,16 @@ def main(argv=None):
     t.add_argument("--source", required=True)
     t.add_argument("--copy-gib", type=float, default=2.0)
     t.add_argument("csvs", nargs=4)
+    ph = sub.add_parser("phases")
+    ph.add_argument("--copy-gib", type=float, default=2.0)
+    ph.add_argument("csvs", nargs=5, help="fetch write copy-fetch copy-write kernel-stats")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy(a.gib)
     elif a.cmd == "traffic":
         traffic(a.kernel, a.source, *a.csvs, copy_gib=a.copy_gib)
+    elif a.cmd == "phases":
+        phases(*a.csvs, copy_gib=a.copy_gib)
     else:
         summarize(a.csv, a.top)
 
