@@ -836,8 +836,10 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     const int w = line - jl * WB;
     const bool active = line < LN && jl < nout;
     const size_t plane_off = (size_t)n1 * PLANE + c0 + w;
-    auto slot_of = [&](int q, bool& cj) {
-        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+    // stored slot of (bb, i; jl, a) and whether it holds the conjugate (lower triangle
+    // of the diagonal block); the summed pairs q = (bb - b0) nocc + i are walked
+    // incrementally, without divisions
+    auto slot_of = [&](int bb, int i, bool& cj) {
         cj = false;
         if (B.diag && bb == B.a) {
             cj = jl < i;
@@ -847,9 +849,9 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     };
     // stage A inputs: rows m2 = sj + r R1 of this line
     cplx<T> xn[R0];
-    auto load_column = [&](int q) {
+    auto load_column = [&](int bb, int i) {
         bool cj;
-        const cplx<T>* src = X + (size_t)(active ? slot_of(q, cj) : 0) * B.ng + plane_off;
+        const cplx<T>* src = X + (size_t)(active ? slot_of(bb, i, cj) : 0) * B.ng + plane_off;
 #pragma unroll
         for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? src[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
     };
@@ -867,14 +869,15 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         pa[r] = bact && B.reuse ? pa_src[(size_t)(sj + r * R0) * NN] : mk<T>(T(0), T(0));
         acc[r] = mk<T>(T(0), T(0));
     }
-    if (q0 < q1) load_column(q0);
+    int bb = B.b0 + q0 / nocc, i = q0 - (q0 / nocc) * nocc;
+    if (q0 < q1) load_column(bb, i);
     cplx<T>* Pb = buf0;
     cplx<T>* Qb = buf1;
     for (int q = q0; q < q1; ++q) {
-        const int bb = B.b0 + q / nocc, i = q - (q / nocc) * nocc;
+        const int bn = i + 1 == nocc ? bb + 1 : bb, in = i + 1 == nocc ? 0 : i + 1;   // pair q + 1
         const bool bside = B.reuse && !(B.diag && bb == B.a);
         bool cj;
-        (void)slot_of(q, cj);
+        (void)slot_of(bb, i, cj);
         if (ha) {
             cplx<T> a[R0];
 #pragma unroll
@@ -883,7 +886,7 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         }
         // in flight during this pair's transform: the next pair's column, this pair's
         // summed orbital and its W block
-        if (q + 1 < q1) load_column(q + 1);
+        if (q + 1 < q1) load_column(bn, in);
         const cplx<T>* ui_src = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
         cplx<T> ui[R1];
 #pragma unroll
@@ -929,6 +932,8 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         cplx<T>* t = Pb;
         Pb = Qb;
         Qb = t;
+        bb = bn;
+        i = in;
     }
     if (bact) {
         cplx<T>* out = Wpart + ((size_t)s * nout + jl) * B.ng + plane_off;
