@@ -298,3 +298,34 @@ def test_madelung_mode_s_gaussian_closed_form_on_gpu():
     for precision, tol in ((pkg.PREC_FP64, 1e-10), (pkg.PREC_FP32_SPLIT, 1e-6)):
         _, out = run_gpu(prob, C, "symmetric", precision=precision, flags=pkg.FLAG_MADELUNG)
         assert abs(out["Ex"][0] - exact) < tol, precision
+
+
+@pytest.mark.parametrize("n", [24, 30, 32, 36, 40, 48])
+@pytest.mark.parametrize("precision", [pkg.PREC_FP32, pkg.PREC_FP32_SPLIT])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_every_specialised_grid_size_complex64(n, precision, mode):
+    """The complex64 pair passes of each compiled grid size (LDS two-stage kernels)
+    against the FP64 oracle to the reduced-precision bars: |dE_x| <= 1e-6 Eh,
+    max |dK~| <= 1e-5, and K_{mu j} within 1e-5 relative."""
+    prob = W.small_problem(kmesh=(1, 2, 1), grid=(n, n, n), nocc=3, counts=(2, 1, 1), seed=40 + n)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, mode)
+    _, out = run_gpu(prob, C, mode, precision=precision, flags=pkg.FLAG_LDS_FFT)
+    assert abs(out["Ex"][0] - ref["Ex"]) <= 1e-6
+    assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5
+    assert rel(out["Kmi"], ref["Kmi"]) < 1e-5
+
+
+@pytest.mark.parametrize("n,precision", [(24, pkg.PREC_FP64), (30, pkg.PREC_FP64), (48, pkg.PREC_FP64),
+                                         (30, pkg.PREC_FP32), (36, pkg.PREC_FP32_SPLIT)])
+def test_omega_gradient_on_specialised_grids(n, precision):
+    """d E_x / d omega from the forward-only sweep (pass 2 without the inverse
+    transforms) on compiled grid sizes, against the oracle's Parseval form."""
+    prob = W.small_problem(kmesh=(1, 2, 1), grid=(n, n, n), nocc=3, counts=(2, 1, 1), seed=90 + n,
+                           kernel=W.KERNEL_ERF_LR, omega=0.35)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, "symmetric")
+    plan, _ = run_gpu(prob, C, "symmetric", precision=precision)
+    _, dw = plan.grad(1.0, want_C=False, want_omega=True)
+    tol = TOL64 if precision == pkg.PREC_FP64 else 1e-5
+    assert abs(dw - ref["dEx_domega"]) < tol * abs(ref["dEx_domega"])
