@@ -891,7 +891,7 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     if (params->kbatch > 0) {
         P->kbatch = std::min(params->kbatch, nk);
     } else {
-        const size_t cap = (size_t)16 << 30;
+        const size_t cap = (size_t)32 << 30;   // exchange buffer of one batch: a whole k row at the paper size in FP64
         P->kbatch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, cap / per_k));
     }
     P->kbatch_max = P->kbatch;
