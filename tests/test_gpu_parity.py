@@ -329,3 +329,27 @@ def test_omega_gradient_on_specialised_grids(n, precision):
     _, dw = plan.grad(1.0, want_C=False, want_omega=True)
     tol = TOL64 if precision == pkg.PREC_FP64 else 1e-5
     assert abs(dw - ref["dEx_domega"]) < tol * abs(ref["dEx_domega"])
+
+
+@pytest.mark.parametrize("case", [
+    dict(kmesh=(1, 1, 1), grid=(1, 8, 6), nocc=1, counts=(2, 1)),        # Gamma only, one orbital, extent 1
+    dict(kmesh=(1, 1, 2), grid=(2, 3, 4), nocc=2, counts=(1, 1)),        # the smallest grid extents
+    dict(kmesh=(1, 2, 1), grid=(10, 9, 8), nocc=16, counts=(2, 2, 1)),   # the largest orbital count
+    dict(kmesh=(1, 1, 2), grid=(12, 10, 9), nocc=8, counts=(1, 1)),      # N_ao = nocc (square C)
+    dict(kmesh=(1, 1, 1), grid=(48, 48, 48), nocc=8, counts=(1, 1)),     # one k-point on a compiled size
+])
+@pytest.mark.parametrize("mode", ["symmetric", "fftfreq"])
+def test_degenerate_shapes(case, mode):
+    """Edge shapes the method admits: a single k-point and orbital, grid extents of 1
+    and 2, 16 occupied orbitals, as many orbitals as AOs."""
+    case = dict(case)
+    prob = W.small_problem(seed=5 + case["nocc"], **case)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, mode)
+    _, out = run_gpu(prob, C, mode)
+    assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+    assert rel(out["K"], ref["K"]) < TOL64
+    assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+    _, o32 = run_gpu(prob, C, mode, precision=pkg.PREC_FP32_SPLIT)
+    assert abs(o32["Ex"][0] - ref["Ex"]) <= 1e-6
+    assert np.max(np.abs(o32["K"] - ref["K"])) <= 1e-5
