@@ -1045,8 +1045,12 @@ occrik_status occrik_plan_autotune(occrik_plan* P, const void* dC, occrik_tune_i
     DeviceGuard guard(P->device);
     hipStream_t s = P->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    OCCRIK_HIP(hipEventCreate(&e0));
-    OCCRIK_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(OCCRIK_ERR_DEVICE, "autotune events");
+    }
+    // settings before tuning, restored if a tuning build fails
+    const int kbatch0 = P->kbatch, nchunks0 = P->nchunks, flags0 = P->params.flags;
     const int saved_profiling = P->profiling;
     P->profiling = 0;
     int builds = 0;
@@ -1137,7 +1141,12 @@ occrik_status occrik_plan_autotune(occrik_plan* P, const void* dC, occrik_tune_i
     (void)hipEventDestroy(e1);
     P->profiling = saved_profiling;
     P->built = false;
-    if (st != OCCRIK_OK) return st;
+    if (st != OCCRIK_OK) {
+        P->kbatch = kbatch0;
+        P->nchunks = nchunks0;
+        P->params.flags = flags0;
+        return st;
+    }
     P->tuned = true;
     if (out) {
         out->kbatch = P->kbatch;
