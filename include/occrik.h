@@ -258,7 +258,8 @@ occrik_status occrik_build_device(occrik_plan *plan, const void *dC, void *dK, v
  * params.kbatch, the FFT flag and params.contract_chunks set to the chosen values
  * builds bitwise the same.  dC as in occrik_build_device (device memory);
  * synchronous; the tuning builds' outputs are discarded (occrik_grad needs a new
- * build).  out may be NULL. */
+ * build).  A batch graph (occrik_batch_create) recorded before tuning keeps replaying
+ * the settings it was recorded with.  out may be NULL. */
 typedef struct {
     int32_t kbatch;               /* chosen k batch */
     int32_t reg_fft;              /* 1: register-resident pair passes chosen */

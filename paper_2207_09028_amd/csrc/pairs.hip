@@ -83,8 +83,10 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
 // the plane is held in registers for the whole row and the next partner's plane is
 // loaded while the current pair is transformed.  The plane transform runs as
 // two-stage lines: stage A of axis n2 on the pair density in registers (lanes
-// along n3), stage B in place, axis n3 from one LDS buffer into a second, and a
-// coalesced copy out of the second.  4 barriers and 8 LDS accesses per point per pair.
+// along n3), stage B in place, axis n3 from one LDS buffer into a second, and its
+// stage B stored straight to memory.  Stage B items are numbered element-fastest,
+// so eight consecutive lanes store 64 contiguous bytes of a row.  3 barriers and
+// 6 LDS accesses per point per pair.
 template <int NN>
 struct P1G {
     static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
@@ -124,9 +126,10 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
     }
     const int tid = threadIdx.x;
     const bool ha = tid < C::NA, hb = tid < C::NBI;
-    const int sj = tid / NN, ln = tid - sj * NN;
+    const int sj = tid / NN, ln = tid - sj * NN;        // stage A items: line-fastest
+    const int bj = tid % R0, bl = tid / R0;             // stage B items: element-fastest
     cplx<T> w[R1 - 1];
-    if (hb) stage_b_twiddles<T, NN>(w, twg + kMaxN, sj);
+    if (hb) stage_b_twiddles<T, NN>(w, twg + kMaxN, bj);
     else {
 #pragma unroll
         for (int r = 0; r < R1 - 1; ++r) w[r] = mk<T>(T(0), T(0));
@@ -156,9 +159,9 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
         __syncthreads();
         if (hb) {
             cplx<T> u[R1];
-            stage_b_load<T, NN>(u, Pb + ln, sj, S);
+            stage_b_load<T, NN>(u, Pb + bl, bj, S);
             stage_b<T, NN, -1>(u, w);
-            stage_b_store<T, NN>(u, Pb + ln, sj, S);
+            stage_b_store<T, NN>(u, Pb + bl, bj, S);
         }
         __syncthreads();
         // axis n3 (lines m2 = ln at stride S, elements adjacent): P -> Q
@@ -168,17 +171,15 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
             stage_a_store<T, NN, -1>(a, Qb + ln * S, sj, 1);
         }
         __syncthreads();
+        // last stage B straight to memory: eight consecutive lanes store elements
+        // m3 = bj + r R0 of row m2 = bl, so a wave writes whole rows over its R1 stores
         if (hb) {
             cplx<T> u[R1];
-            stage_b_load<T, NN>(u, Qb + ln * S, sj, 1);
+            stage_b_load<T, NN>(u, Qb + bl * S, bj, 1);
             stage_b<T, NN, -1>(u, w);
-            stage_b_store<T, NN>(u, Qb + ln * S, sj, 1);
-        }
-        __syncthreads();
-        cplx<T>* out = X + (size_t)slot * B.ng + (size_t)n1 * PLANE;
-        for (int e = tid; e < PLANE; e += NT) {
-            const int m2 = e / NN, m3 = e - m2 * NN;
-            out[e] = Qb[m2 * S + m3];
+            cplx<T>* out = X + (size_t)slot * B.ng + (size_t)n1 * PLANE + (size_t)bl * NN + bj;
+#pragma unroll
+            for (int r = 0; r < R1; ++r) out[r * R0] = u[r];
         }
     }
 }
