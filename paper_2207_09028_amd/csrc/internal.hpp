@@ -43,6 +43,8 @@ struct PairBatch {
     int parseval;             // 1: accumulate sum f |u^|^2 per pass-2 workgroup
     int regfft;               // REGFFT_PASS* bits: passes run with register-resident line FFTs
     void* kvals;              // [nb][m2][m1][m3] kernel values of the batch, working precision (plan workspace)
+    int kcache;               // 1: kvals is the plan's table of every k-point difference k_a - k_b
+                              //    ([(2M1-1)(2M2-1)(2M3-1)][m2][m1][m3]), filled once per omega
     // Orbital sources of the passes (working precision, complex).  The density of a
     // slot is conj(D_{i b}) O_j and the a-side sum is W_j += A_{i b} Vt_ij, with
     //   D_{i b} = psi[(b kstride + i) ng]   (the psi argument of the launchers)
@@ -81,6 +83,11 @@ hipError_t launch_pass1_reg(const PairBatch& B, const cplx<float>* psi, cplx<flo
 hipError_t launch_pass2_reg(const PairBatch& B, cplx<float>* X, double* parts, int deriv_only, hipStream_t s);
 hipError_t launch_pass3_reg(const PairBatch& B, const cplx<float>* X, const cplx<float>* psi, cplx<float>* Wpart,
                             cplx<float>* W, hipStream_t s);
+
+// the plan's cache of kernel values: f(|G+q|) for every k-point difference q of the mesh
+template <typename T>
+hipError_t launch_kcache(const PairBatch& B, void* out, hipStream_t s);
+size_t kcache_tables(int M1, int M2, int M3);
 
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);

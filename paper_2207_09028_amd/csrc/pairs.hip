@@ -189,14 +189,13 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
 // ---------------------------------------------------------------------------
 // kernel values of a batch: f(|G+q|) (or df/domega) for every summed k_b, with the
 // Nyquist-plane mean of the symmetric mode, laid out [b - b0][m2][m1][m3] so that
-// both forms of pass 2 read them coalesced; evaluated in the working precision
+// every form of pass 2 reads them coalesced; evaluated in the working precision
 // (the truncated kernels in FP64)
 template <typename T>
 __global__ void __launch_bounds__(256) kvals_kernel(PairBatch B, T* __restrict__ out, int deriv_only) {
     const int N1 = B.N1, N2 = B.N2, N3 = B.N3;
     const size_t per_b = (size_t)N1 * N2 * N3;
     const size_t total = (size_t)B.nb * per_b;
-    const bool sym = B.nyquist == OCCRIK_NYQUIST_SYMMETRIC;
     Recip<T> rc;
 #pragma unroll
     for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
@@ -209,16 +208,28 @@ __global__ void __launch_bounds__(256) kvals_kernel(PairBatch B, T* __restrict__
         const int i2 = r / (N1 * N3), rem = r - i2 * (N1 * N3), i1 = rem / N3, i3 = rem - i1 * N3;
         double qb[3];
         kfrac_of(B.b0 + bi, B.M1, B.M2, B.M3, qb);
-        const double q0 = qa[0] - qb[0], q1 = qa[1] - qb[1], q2 = qa[2] - qb[2];
-        const int m1 = freq(i1, N1), m2 = freq(i2, N2), m3 = freq(i3, N3);
-        T f = kernel_at<T>(B, rc, q0, q1, q2, m1, m2, m3, deriv_only, om);
-        if (sym && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3))) {
-            const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
-            const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
-            const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
-            f = T(0.5) * (f + kernel_at<T>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv_only, om));
-        }
-        out[e] = f;
+        out[e] = kernel_value<T>(B, rc, qa[0] - qb[0], qa[1] - qb[1], qa[2] - qb[2], i1, i2, i3, deriv_only, om);
+    }
+}
+
+// the same values for every k-point difference of the mesh, q_d = (kappa_a - kappa_b)_d / M_d,
+// laid out [difference index][m2][m1][m3] (kv_block gives the index of a pair of k-points)
+template <typename T>
+__global__ void __launch_bounds__(256) kcache_kernel(PairBatch B, T* __restrict__ out, int nq) {
+    const int N1 = B.N1, N2 = B.N2, N3 = B.N3;
+    const size_t per_q = (size_t)N1 * N2 * N3;
+    const size_t total = (size_t)nq * per_q;
+    const int D2 = 2 * B.M2 - 1, D3 = 2 * B.M3 - 1;
+    Recip<T> rc;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) rc.b[d] = T(B.recip[d]);
+    const T om = T(B.omega);
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int qi = (int)(e / per_q);
+        const int r = (int)(e - (size_t)qi * per_q);
+        const int i2 = r / (N1 * N3), rem = r - i2 * (N1 * N3), i1 = rem / N3, i3 = rem - i1 * N3;
+        const int d1 = qi / (D2 * D3) - (B.M1 - 1), d2 = (qi / D3) % D2 - (B.M2 - 1), d3 = qi % D3 - (B.M3 - 1);
+        out[e] = kernel_value<T>(B, rc, double(d1) / B.M1, double(d2) / B.M2, double(d3) / B.M3, i1, i2, i3, false, om);
     }
 }
 
@@ -258,7 +269,7 @@ __global__ void __launch_bounds__(kFftThreads) pass2_kernel(PairBatch B, cplx<T>
 
     // kernel values of this slab from the batch's table, shared by every pair of the group
     const int tile_sz = N1 * N3;
-    const T* kv = static_cast<const T*>(B.kvals) + ((size_t)(b - B.b0) * N2 + m2i) * tile_sz;
+    const T* kv = static_cast<const T*>(B.kvals) + ((size_t)kv_block(B, b) * N2 + m2i) * tile_sz;
     T v[VI];
 #pragma unroll
     for (int t = 0; t < VI; ++t) {
@@ -396,7 +407,7 @@ __global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T
     cplx<T> w[R1 - 1];
     T v[R1];
     {
-        const T* kv = static_cast<const T*>(B.kvals) + ((size_t)(b - B.b0) * NN + m2i) * rs;
+        const T* kv = static_cast<const T*>(B.kvals) + ((size_t)kv_block(B, b) * NN + m2i) * rs;
         if (hb) {
             stage_b_twiddles<T, NN>(w, twg, bj);
 #pragma unroll
@@ -1025,6 +1036,17 @@ void launch_pass3s(const PairBatch& B, const cplx<T>* X, cplx<T>* Wpart, cplx<T>
 
 }  // namespace
 
+size_t kcache_tables(int M1, int M2, int M3) { return (size_t)(2 * M1 - 1) * (2 * M2 - 1) * (2 * M3 - 1); }
+
+template <typename T>
+hipError_t launch_kcache(const PairBatch& B, void* out, hipStream_t s) {
+    const int nq = (int)kcache_tables(B.M1, B.M2, B.M3);
+    const size_t nv = (size_t)nq * B.ng;
+    const unsigned grid = (unsigned)std::min<size_t>((nv + 255) / 256, 65536);
+    hipLaunchKernelGGL((kcache_kernel<T>), dim3(grid), dim3(256), 0, s, B, static_cast<T*>(out), nq);
+    return hipGetLastError();
+}
+
 int pair_groups(const PairBatch& B) {
     const int nn = B.nocc * B.nout;
     const int gd = B.diag ? (B.ntri + B.group - 1) / B.group : 0;
@@ -1051,8 +1073,8 @@ hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, cons
 template <typename T>
 hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, double* parts, int deriv_only,
                         hipStream_t s) {
-    if (!B.kvals) return hipErrorInvalidValue;
-    {
+    if (!B.kvals || (B.kcache && deriv_only)) return hipErrorInvalidValue;   // the cache holds f only
+    if (!B.kcache) {
         const size_t nv = (size_t)B.nb * B.ng;
         const unsigned kgrid = (unsigned)std::min<size_t>((nv + 255) / 256, 16384);
         hipLaunchKernelGGL((kvals_kernel<T>), dim3(kgrid), dim3(256), 0, s, B, static_cast<T*>(B.kvals), deriv_only);
@@ -1147,6 +1169,7 @@ hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s) {
     template hipError_t launch_pass2<T>(const PairBatch&, cplx<T>*, const cplx<T>*, double*, int, hipStream_t);   \
     template hipError_t launch_pass3<T>(const PairBatch&, const cplx<T>*, const cplx<T>*, cplx<T>*, cplx<T>*,  \
                                         const cplx<T>*, hipStream_t);                                           \
+    template hipError_t launch_kcache<T>(const PairBatch&, void*, hipStream_t);                              \
     template hipError_t launch_wreduce<T>(const PairBatch&, const cplx<T>*, cplx<T>*, hipStream_t);            \
     template hipError_t launch_fill_zero<T>(cplx<T>*, size_t, hipStream_t);
 OCCRIK_INST(float)

@@ -133,6 +133,33 @@ __device__ inline T kernel_at(const PairBatch& B, const Recip<T>& rc, double q0,
     return deriv ? kernel_dfdw<T>(x2, B.kernel, om) : kernel_f<T>(x2, B.kernel, om);
 }
 
+// Table block of summed k-point b in the batch's kernel values: (b - b0) for a
+// per-batch table, or with the plan's cache the index of the difference k_a - k_b
+// (each component in [-(M - 1), M - 1], row-major over the three directions).
+__device__ inline int kv_block(const PairBatch& B, int b) {
+    if (!B.kcache) return b - B.b0;
+    const int a3 = B.a % B.M3, a2 = (B.a / B.M3) % B.M2, a1 = B.a / (B.M2 * B.M3);
+    const int b3 = b % B.M3, b2 = (b / B.M3) % B.M2, b1 = b / (B.M2 * B.M3);
+    return ((a1 - b1 + B.M1 - 1) * (2 * B.M2 - 1) + (a2 - b2 + B.M2 - 1)) * (2 * B.M3 - 1) + (a3 - b3 + B.M3 - 1);
+}
+
+// f (or df/domega) at grid index (i1, i2, i3) for momentum q (fractional), with the
+// Nyquist-plane mean of the symmetric mode
+template <typename T>
+__device__ inline T kernel_value(const PairBatch& B, const Recip<T>& rc, double q0, double q1, double q2, int i1,
+                                 int i2, int i3, bool deriv, T om) {
+    const int N1 = B.N1, N2 = B.N2, N3 = B.N3;
+    const int m1 = freq(i1, N1), m2 = freq(i2, N2), m3 = freq(i3, N3);
+    T f = kernel_at<T>(B, rc, q0, q1, q2, m1, m2, m3, deriv, om);
+    if (B.nyquist == OCCRIK_NYQUIST_SYMMETRIC && ((2 * m1 == -N1) || (2 * m2 == -N2) || (2 * m3 == -N3))) {
+        const int mm1 = (2 * m1 == -N1) ? -m1 : m1;
+        const int mm2 = (2 * m2 == -N2) ? -m2 : m2;
+        const int mm3 = (2 * m3 == -N3) ? -m3 : m3;
+        f = T(0.5) * (f + kernel_at<T>(B, rc, q0, q1, q2, mm1, mm2, mm3, deriv, om));
+    }
+    return f;
+}
+
 // Sizes: compile-time when NN > 0 (cubic NN^3 grid), else taken from the batch.
 template <int NN>
 struct Dims {

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(RegCfg<NN>::NT) pass2r_kernel(PairBatch B, cpl
 
     // kernel values at this lane's (m1, m2, m3 = line) points, shared by the whole group;
     // re-read per pair (cache hits) rather than held, which keeps the kernel at 3 waves/SIMD
-    const float* kv = static_cast<const float*>(B.kvals) + ((size_t)(b - B.b0) * NN + m2i) * PLANE + line;
+    const float* kv = static_cast<const float*>(B.kvals) + ((size_t)kv_block(B, b) * NN + m2i) * PLANE + line;
     const T scale = T(B.inv_ng);
     cplx<T>* Lp = L + p * NN * S;
     double acc = 0.0;

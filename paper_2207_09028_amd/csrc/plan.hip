@@ -101,6 +101,9 @@ struct occrik_plan {
     void* tw = nullptr;        // [3][kMaxN]
     double* parts = nullptr;   // [kbatch * nocc^2 * N2]
     void* kvals = nullptr;     // [kbatch][ng] kernel values of a batch, working precision
+    void* kcache = nullptr;    // kernel values of every k-point difference (see PairBatch::kcache), or null
+    bool kcache_valid = false; // filled for kcache_omega
+    double kcache_omega = 0.0;
     // collocation: image tables (whole plan) and per-chunk scratch
     double4* cimg = nullptr;   // images of every shell, bucketed by image cell
     int* cbucket = nullptr;    // [nshell][nk + 1] offsets into cimg
@@ -493,6 +496,10 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb, bool occ_only 
                : (P->params.flags & OCCRIK_FLAG_REG_FFT_ALL) ? (REGFFT_PASS1 | REGFFT_PASS2 | REGFFT_PASS3)
                                                               : REGFFT_DEFAULT;
     B.kvals = P->kvals;
+    if (P->kcache && !occ_only) {
+        B.kvals = P->kcache;
+        B.kcache = 1;
+    }
     const char* psi = static_cast<const char*>(P->psi);
     B.outp = psi + (size_t)a * B.kstride * B.ng * P->elem;
     B.accp = psi;
@@ -530,6 +537,17 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
     }
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
     OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
+    // kernel values of every k-point difference, once per omega; under stream capture the
+    // fill is recorded into the graph (and replayed with it) and the plan stays unfilled
+    if (P->kcache && (!P->kcache_valid || P->kcache_omega != P->params.omega)) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        OCCRIK_HIP(hipStreamIsCapturing(s, &cs));
+        OCCRIK_HIP(launch_kcache<T>(make_batch(P, 0, 0, 1), P->kcache, s));
+        if (cs == hipStreamCaptureStatusNone) {
+            P->kcache_valid = true;
+            P->kcache_omega = P->params.omega;
+        }
+    }
     int64_t launches = 1;
     const bool reuse = plan_reuses_pairs(P);
     for (int a = 0; a < nk; ++a) {
@@ -947,6 +965,17 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     A(&P->tw, 3 * kMaxN * P->elem);
     A((void**)&P->parts, sizeof(double) * max_groups * P->N[1]);
     A(&P->kvals, P->elem / 2 * (size_t)P->kbatch * ng);
+    // kernel values of every k-point difference when they take at most 2 GiB (at the paper
+    // size 1331 tables, 0.59 GB in FP32); otherwise every batch evaluates its own
+    {
+        const size_t kc = P->elem / 2 * kcache_tables(P->M[0], P->M[1], P->M[2]) * ng;
+        if (e == hipSuccess && kc <= ((size_t)2 << 30)) {
+            if (P->alloc(&P->kcache, kc) != hipSuccess) {
+                (void)hipGetLastError();
+                P->kcache = nullptr;
+            }
+        }
+    }
     A((void**)&P->Kpart, sizeof(double2) * (size_t)nk * nao * nout * P->nchunks);
     P->kpart_chunks = P->nchunks;
     A((void**)&P->Kmi, sizeof(double2) * (size_t)nk * nao * nout);
