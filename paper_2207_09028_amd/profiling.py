@@ -91,7 +91,7 @@ def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, cfetch_csv
 
 
 def phases(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str, stats_csv: str,
-           kernels=("pass1", "pass2", "pass3", "wreduce", "kvals", "orbitals_mfma", "contract_mfma"),
+           kernels=("pass1", "pass2", "pass3", "wreduce", "kvals", "kcache", "orbitals_mfma", "contract_mfma"),
            copy_gib: float = 2.0):
     """Measured HBM bytes per dispatch (counters, copy-calibrated) and achieved GB/s over the
     kernel-trace average duration, for every kernel whose name contains one of ``kernels``."""
