@@ -251,28 +251,56 @@ __global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__
                 }
             }
         } else {
-            // 32 real k values per step = 16 grid points; this lane holds 4 consecutive points
+            // 32 real k values per step = 16 grid points; this lane holds 4 consecutive points.
+            // Whole steps load them as two 16-byte vectors when every row stride and offset is
+            // even (then, with steps on multiples of 4 points, each load is 16-byte aligned);
+            // otherwise, and for the ragged last step of a chunk, point by point.
             int step = 0;
+            const bool mu_ok = mu < nao;
+            const bool vec = ((ldc | (size_t)ng | (size_t)chi_n0) & 1) == 0;
             for (int n = n0; n < n1; n += 16) {
                 const int nb = n + 4 * (l >> 4);
+                const bool whole = vec && n + 16 <= n1;
                 float av[8];
+                if (whole) {
+                    const float4* s4 = reinterpret_cast<const float4*>(chir + 2 * (size_t)nb);
+                    const float4 x0 = s4[0], x1 = s4[1];
+                    const float z = mu_ok ? 1.f : 0.f;
+                    av[0] = z * x0.x; av[1] = z * x0.y; av[2] = z * x0.z; av[3] = z * x0.w;
+                    av[4] = z * x1.x; av[5] = z * x1.y; av[6] = z * x1.z; av[7] = z * x1.w;
+                } else {
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const bool ok = nb + p < n1 && mu < nao;
-                    av[2 * p] = ok ? (float)chir[2 * (size_t)(nb + p)] : 0.f;
-                    av[2 * p + 1] = ok ? (float)chir[2 * (size_t)(nb + p) + 1] : 0.f;
+                    for (int p = 0; p < 4; ++p) {
+                        const bool ok = nb + p < n1 && mu_ok;
+                        av[2 * p] = ok ? (float)chir[2 * (size_t)(nb + p)] : 0.f;
+                        av[2 * p + 1] = ok ? (float)chir[2 * (size_t)(nb + p) + 1] : 0.f;
+                    }
                 }
 #pragma unroll
                 for (int rt = 0; rt < kMaxRowTiles; ++rt) {
                     if (rt < ct_n) {
                         const int col = rt * 16 + (l & 15), j = col >> 1, cp = col & 1;
                         float bv[8];
+                        if (whole) {
+                            const int jc = j < nocc ? j : nocc - 1;
+                            const float4* w4 = reinterpret_cast<const float4*>(Wk + (size_t)jc * ng + nb);
+                            const float4 y0 = w4[0], y1 = w4[1];
+                            const float z = j < nocc ? 1.f : 0.f;
+                            const float wr[4] = {z * y0.x, z * y0.z, z * y1.x, z * y1.z};
+                            const float wi[4] = {z * y0.y, z * y0.w, z * y1.y, z * y1.w};
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            cplx<T> w = mk<T>(T(0), T(0));
-                            if (nb + p < n1 && j < nocc) w = Wk[(size_t)j * ng + nb + p];
-                            bv[2 * p] = cp == 0 ? (float)w.x : (float)w.y;
-                            bv[2 * p + 1] = cp == 0 ? (float)w.y : -(float)w.x;
+                            for (int p = 0; p < 4; ++p) {
+                                bv[2 * p] = cp == 0 ? wr[p] : wi[p];
+                                bv[2 * p + 1] = cp == 0 ? wi[p] : -wr[p];
+                            }
+                        } else {
+#pragma unroll
+                            for (int p = 0; p < 4; ++p) {
+                                cplx<T> w = mk<T>(T(0), T(0));
+                                if (nb + p < n1 && j < nocc) w = Wk[(size_t)j * ng + nb + p];
+                                bv[2 * p] = cp == 0 ? (float)w.x : (float)w.y;
+                                bv[2 * p + 1] = cp == 0 ? (float)w.y : -(float)w.x;
+                            }
                         }
                         acc[rt] = mfma_split(av, bv, acc[rt]);
                     }
