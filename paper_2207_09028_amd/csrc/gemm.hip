@@ -152,10 +152,14 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll
                 for (int t = 0; t < kOrbTiles; ++t) {
                     const int n = nbase + 16 * t + (l & 15);
+                    // (re, im) of one AO at this point in one 8-byte load (kk0 is even)
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
-                        const int kk = kk0 + v, mu = m0 + (kk >> 1), cc = kk & 1;
-                        bv[t][v] = (mu < nao && n < cnt) ? (float)chir[2 * ((size_t)mu * ldc + n) + cc] : 0.f;
+                    for (int v = 0; v < 8; v += 2) {
+                        const int mu = m0 + ((kk0 + v) >> 1);
+                        cplx<T> x = mk<T>(T(0), T(0));
+                        if (mu < nao && n < cnt) x = *reinterpret_cast<const cplx<T>*>(chir + 2 * ((size_t)mu * ldc + n));
+                        bv[t][v] = (float)x.x;
+                        bv[t][v + 1] = (float)x.y;
                     }
                 }
 #pragma unroll
