@@ -10,7 +10,7 @@
 //   contract   D[mu][2j + c'] = sum_{2n + c} chi_c(mu, n) B[2n + c][2j + c'],
 //              B = [[Re W, Im W], [Im W, -Re W]] per (n, j)
 // and run as 16 x 16 MFMA tiles:
-//   MODE 0  FP64 data, v_mfma_f64_16x16x4_f64
+//   MODE 0  FP64 data, v_mfma_f64_16x16x4_f64 (the contraction: 8 points per step)
 //   MODE 1  FP32 data, v_mfma_f32_16x16x4_f32
 //   MODE 2  FP32 data split into three bf16 terms x = h + m + l per operand,
 //           v_mfma_f32_16x16x32_bf16 on the six products hh, hm, mh, hl, lh, mm
@@ -24,7 +24,9 @@
 //
 // The contraction splits the grid sum into chunks; each chunk is accumulated
 // in the working precision and the chunk partials are added in FP64 in a fixed
-// order.  Both kernels stream the Bloch AOs once and are bandwidth-bound for
+// order.  Its FP32 forms consume 16 grid points per step, each lane loading 4
+// consecutive points of its AO row and of W as 16-byte vectors; MODE 1 issues
+// eight 16x16x4 products for them, MODE 2 the six split-bf16 16x16x32 products.  Both kernels stream the Bloch AOs once and are bandwidth-bound for
 // the few occupied columns involved.
 #include "internal.hpp"
 
@@ -65,6 +67,15 @@ __device__ __forceinline__ f4 mfma4<1>(double a, double b, f4 c) {
 }
 
 // six-product split-bf16 step over 8 k values per lane
+// 32 real k values as eight FP32 16x16x4 products: lane group g supplies its value s as
+// the k index g of product s (the same assignment for both operands, so the sum over k
+// is only reordered)
+__device__ __forceinline__ f4 mfma_x8(const float* a, const float* b, f4 c) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v], b[v], c, 0, 0, 0);
+    return c;
+}
+
 __device__ __forceinline__ f4 mfma_split(const float* a, const float* b, f4 c) {
     bf8 ah, am, al, bh, bm, bl;
 #pragma unroll
@@ -228,29 +239,35 @@ __global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__
         }
     };
     if (mu0 < nao) {
-        if constexpr (MODE < 2) {
-            // 4 real k values per step = 2 grid points
-            int step = 0;
-            for (int n = n0; n < n1; n += 2) {
-                const int nn = n + ((l >> 4) >> 1), cc = (l >> 4) & 1;
-                const bool ok = nn < n1;
-                const T a = (ok && mu < nao) ? chir[2 * (size_t)nn + cc] : T(0);
+        if constexpr (MODE == 0) {
+            // 16 real k values per step = 8 grid points: lane group g holds the 2 consecutive
+            // points n + 2g, n + 2g + 1 (re, im of each) and supplies its value s as the k
+            // index g of the s-th 16x16x4 product
+            const bool mu_ok = mu < nao;
+            for (int n = n0; n < n1; n += 8) {
+                const int nb = n + 2 * (l >> 4);
+                double av[4];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    cplx<T> x = mk<T>(T(0), T(0));
+                    if (mu_ok && nb + p < n1) x = *reinterpret_cast<const cplx<T>*>(chir + 2 * (size_t)(nb + p));
+                    av[2 * p] = x.x;
+                    av[2 * p + 1] = x.y;
+                }
 #pragma unroll
                 for (int rt = 0; rt < kMaxRowTiles; ++rt) {
                     if (rt < ct_n) {
                         const int col = rt * 16 + (l & 15), j = col >> 1, cp = col & 1;
-                        T b = T(0);
-                        if (ok && j < nocc) {
-                            const cplx<T> w = Wk[(size_t)j * ng + nn];
-                            b = cp == 0 ? (cc == 0 ? w.x : w.y) : (cc == 0 ? w.y : -w.x);
+                        double bv[4];
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) {
+                            cplx<T> w = mk<T>(T(0), T(0));
+                            if (j < nocc && nb + p < n1) w = Wk[(size_t)j * ng + nb + p];
+                            bv[2 * p] = cp == 0 ? w.x : w.y;
+                            bv[2 * p + 1] = cp == 0 ? w.y : -w.x;
                         }
-                        acc[rt] = mfma4<MODE>(a, b, acc[rt]);
-                    }
-                }
-                if constexpr (MODE == 1) {
-                    if (++step == kFlush) {
-                        flush();
-                        step = 0;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[rt] = mfma4<MODE>(av[v], bv[v], acc[rt]);
                     }
                 }
             }
@@ -306,7 +323,8 @@ __global__ void __launch_bounds__(256) contract_mfma(const cplx<T>* __restrict__
                                 bv[2 * p + 1] = cp == 0 ? (float)w.y : -(float)w.x;
                             }
                         }
-                        acc[rt] = mfma_split(av, bv, acc[rt]);
+                        if constexpr (MODE == 2) acc[rt] = mfma_split(av, bv, acc[rt]);
+                        else acc[rt] = mfma_x8(av, bv, acc[rt]);
                     }
                 }
                 if (++step == kFlush / 8) {
