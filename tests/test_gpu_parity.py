@@ -353,3 +353,21 @@ def test_degenerate_shapes(case, mode):
     _, o32 = run_gpu(prob, C, mode, precision=pkg.PREC_FP32_SPLIT)
     assert abs(o32["Ex"][0] - ref["Ex"]) <= 1e-6
     assert np.max(np.abs(o32["K"] - ref["K"])) <= 1e-5
+
+
+@pytest.mark.parametrize("nocc,n,kmesh", [(1, 24, (1, 2, 2)), (2, 36, (2, 1, 1)), (7, 32, (1, 1, 2)),
+                                          (6, 40, (1, 2, 1))])
+@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT])
+def test_compiled_sizes_with_other_orbital_counts(nocc, n, kmesh, precision):
+    """Rows of the diagonal block with 1..nocc stored pairs, odd and even orbital
+    counts and partial orbital groups in the compiled-size pair passes."""
+    prob = W.small_problem(kmesh=kmesh, grid=(n, n, n), nocc=nocc, counts=(2, 2, 1), seed=120 + nocc)
+    C = W.random_coefficients(prob)
+    ref = oracle_result(prob, C, "symmetric")
+    _, out = run_gpu(prob, C, "symmetric", precision=precision)
+    if precision == pkg.PREC_FP64:
+        assert rel(out["Kmi"], ref["Kmi"]) < TOL64
+        assert abs(out["Ex"][0] - ref["Ex"]) < TOL64 * abs(ref["Ex"])
+    else:
+        assert abs(out["Ex"][0] - ref["Ex"]) <= 1e-6
+        assert np.max(np.abs(out["K"] - ref["K"])) <= 1e-5
