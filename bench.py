@@ -100,17 +100,20 @@ def pass_kernel_names(info, precision):
 def measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from a committed rocprofv3 --pmc summary under
     profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None when no
-    summary covers it or the kernel's source has changed since the counters were taken."""
+    summary covers it or the kernel's source or its launch set-up has changed since the
+    counters were taken."""
     import glob
-    import hashlib
-    from paper_2207_09028_amd.profiling import read_traffic
+    from paper_2207_09028_amd.profiling import read_traffic, sources_sha256
     here = os.path.dirname(os.path.abspath(__file__))
     for path in sorted(glob.glob(os.path.join(here, "profiles", "*pmc*.md"))):
         t = read_traffic(path)
         if t.get("kernel") != kernel or "source" not in t:
             continue
-        src = os.path.join(here, t["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != t.get("source_sha256"):
+        try:
+            sha = sources_sha256(t["source"], here)
+        except OSError:
+            return None
+        if sha != t.get("source_sha256"):
             return None
         return float(t["hbm_bytes_per_launch"])
     return None

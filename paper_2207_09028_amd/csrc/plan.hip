@@ -481,7 +481,18 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb, bool occ_only 
     B.ntri = P->nocc * (P->nocc + 1) / 2;
     const int nn = B.nocc * B.nout;
     B.nslots = B.diag ? B.ntri + (nb - 1) * nn : nb * nn;
+    // stored pairs per pass-2 workgroup, complex64: up to 4 x nout (a workgroup's set-up,
+    // its kernel values, twiddles and first slab load, is shared by more pairs) while the
+    // launch keeps at least 2048 workgroups; never fewer pairs than the plan's own group (the
+    // partial-sum buffer of the omega sweep is sized for that). Complex128 keeps the plan's
+    // group: its pass 2 measured slower with the larger ones.
     B.group = P->group;
+    for (int f = 4; f > 1 && !P->fp64; f /= 2) {
+        if ((size_t)B.N2 * nb * nn / ((size_t)P->group * f) >= 2048) {
+            B.group = P->group * f;
+            break;
+        }
+    }
     B.kernel = P->params.kernel;
     B.nyquist = P->params.nyquist;
     B.omega = P->params.omega;

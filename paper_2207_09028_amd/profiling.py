@@ -6,12 +6,13 @@
         kernels (bytes counted per byte actually moved);
     python -m paper_2207_09028_amd.profiling summarize <kernel_stats.csv> [--top 12]
         a short text table of a rocprofv3 --stats kernel summary;
-    python -m paper_2207_09028_amd.profiling traffic --kernel NAME --source FILE \
+    python -m paper_2207_09028_amd.profiling traffic --kernel NAME --source FILE[,FILE...] \
             <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv>
         HBM bytes per dispatch of one kernel from two rocprofv3 --pmc runs
         (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for
         the plain copy above; prints "key: value" lines that bench.py reads back
-        (with the SHA-256 of the kernel's source, so a changed kernel reads as
+        (with one SHA-256 over the kernel's source and the files that set its
+        launch, in the order given, so a changed kernel or launch reads as
         unmeasured);
     python -m paper_2207_09028_amd.profiling phases <fetch.csv> <write.csv> \
             <copy_fetch.csv> <copy_write.csv> <kernel_stats.csv>
@@ -69,6 +70,17 @@ def _copy_scale(path: str, counter: str, nbytes: int):
     return nbytes / (val * 1024.0) if val else float("nan")
 
 
+def sources_sha256(sources: str, root: str = "") -> str:
+    """SHA-256 over the bytes of the comma-separated files ``sources``, concatenated in order."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    for f in sources.split(","):
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str,
             copy_gib: float = 2.0):
     import hashlib
@@ -77,7 +89,7 @@ def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, cfetch_csv
     ws = _copy_scale(cwrite_csv, "WRITE_SIZE", nbytes)
     f, nf = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
     w, nw = _counter_per_dispatch(write_csv, "WRITE_SIZE", kernel)
-    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    sha = sources_sha256(source)
     total = f * 1024.0 * fs + w * 1024.0 * ws
     print(f"kernel: {kernel}")
     print(f"source: {source}")

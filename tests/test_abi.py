@@ -104,3 +104,17 @@ def test_null_arguments_are_rejected():
     assert lib.occrik_conventional_k(None, 2, None, None, None) == 1
     assert lib.occrik_last_error_k(None) == -1
     lib.occrik_plan_destroy(None)
+
+
+def test_profile_traffic_reads_as_unmeasured_after_a_change(tmp_path):
+    """The committed HBM-counter summaries count only while the hashed sources are unchanged:
+    the hash covers every listed file, in order."""
+    import hashlib
+    from paper_2207_09028_amd.profiling import sources_sha256
+    (tmp_path / "a").write_bytes(b"kernel")
+    (tmp_path / "b").write_bytes(b"launch")
+    h = sources_sha256("a,b", str(tmp_path))
+    assert h == hashlib.sha256(b"kernellaunch").hexdigest()
+    assert sources_sha256("b,a", str(tmp_path)) != h
+    (tmp_path / "b").write_bytes(b"launch2")
+    assert sources_sha256("a,b", str(tmp_path)) != h
