@@ -1095,10 +1095,20 @@ hipError_t launch_pass2(const PairBatch& B, cplx<T>* X, const cplx<T>* tw, doubl
 }
 
 int pass3_splits(const PairBatch& B, int elem) {
-    const int target_wg = 2048;
+    // at least ~2048 workgroups; then, within twice that split count, the first whose
+    // workgroup count is a whole number of rounds over the 256 compute units: the compiled
+    // complex64 kernels hold one 1024-thread workgroup per CU, every workgroup walks the
+    // same number of pairs, and a last round that fills part of the chip is idle time.
+    // The count depends on the batch only through its cap, so a plan's Wpart buffer,
+    // sized for its largest batch, holds every smaller batch's partial sums.
+    const int target_wg = 2048, cus = 256;
     const int nn = specialised(B);
     const int base_wg = nn > 0 && B.nout <= 16 ? nn * (nn / colblock(nn, elem)) : B.N1 * B.nout;
-    return std::max(1, std::min(B.nb * B.nocc, (target_wg + base_wg - 1) / base_wg));
+    const int s0 = (target_wg + base_wg - 1) / base_wg;
+    int sp = s0;
+    while ((size_t)base_wg * sp % cus != 0 && sp < 2 * s0) ++sp;
+    if ((size_t)base_wg * sp % cus != 0) sp = s0;
+    return std::max(1, std::min(B.nb * B.nocc, sp));
 }
 
 template <typename T>
