@@ -802,9 +802,10 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
 // Pass 3 for the compiled cubic sizes with at most 8 output orbitals: the column
 // block transform along m2 as two-stage lines, stage A fed from the prefetched
 // registers and stage B kept in registers, where the a-side sum (and the b-side
-// product) is formed; two LDS buffers alternate between summed pairs.  Per pair:
-// one barrier (two with the b-side sum) and 2 LDS accesses per point, against
-// six barriers and 6 accesses in pass3f_kernel.  Used for complex64.
+// product) is formed.  Three LDS buffers rotate between summed pairs, so that the
+// b-side sum over a pair's partner orbitals is read one pair later, behind the
+// next pair's only barrier: per pair one barrier and 2 LDS accesses per point,
+// against six barriers and 6 accesses in pass3f_kernel.  Used for complex64.
 template <typename T, int NN>
 struct P3S {
     static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
@@ -827,7 +828,6 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     constexpr int BPT = (BP + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* buf1 = buf0 + NN * LNP;
     const int n1 = blockIdx.x % NN;
     const int cb = (blockIdx.x / NN) % NCB;
     const int s = blockIdx.x / (NN * NCB);
@@ -883,8 +883,26 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     }
     int bb = B.b0 + q0 / nocc, i = q0 - (q0 / nocc) * nocc;
     if (q0 < q1) load_column(bb, i);
+    // Pb: this pair's buffer; Rb: the previous pair's, whose b-side products are summed
+    // behind this pair's barrier (written before it, rewritten two pairs later, after
+    // the barrier that follows the sum)
     cplx<T>* Pb = buf0;
-    cplx<T>* Qb = buf1;
+    cplx<T>* Rb = buf0 + 2 * NN * LNP;
+    bool pending = false;                               // the previous pair's b-side sum is due
+    cplx<T> wprev[BPT];
+    cplx<T>* wout_prev = W;
+    auto bside_sum = [&](const cplx<T>* Sb, const cplx<T>* wv_in, cplx<T>* dst) {
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int e = tid + t * NT;
+            if (e < BP) {
+                const int n2 = e / WB, ww = e - n2 * WB;
+                cplx<T> sum = wv_in[t];
+                for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, Sb[n2 * LNP + j * WB + ww]);
+                dst[(size_t)n2 * NN + ww] = sum;
+            }
+        }
+    };
     for (int q = q0; q < q1; ++q) {
         const int bn = i + 1 == nocc ? bb + 1 : bb, in = i + 1 == nocc ? 0 : i + 1;   // pair q + 1
         const bool bside = B.reuse && !(B.diag && bb == B.a);
@@ -912,6 +930,7 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
             wv[t] = bside && e < BP ? wout[(size_t)n2 * NN + ww] : mk<T>(T(0), T(0));
         }
         __syncthreads();
+        if (pending) bside_sum(Rb, wprev, wout_prev);
         if (hb) {
             cplx<T> y[R1];
             stage_b_load<T, NN>(y, Pb + line, sj, LNP);
@@ -928,24 +947,18 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
                 }
             }
         }
-        if (bside) {
-            __syncthreads();
+        pending = bside;
 #pragma unroll
-            for (int t = 0; t < BPT; ++t) {
-                const int e = tid + t * NT;
-                if (e < BP) {
-                    const int n2 = e / WB, ww = e - n2 * WB;
-                    cplx<T> sum = wv[t];
-                    for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, Pb[n2 * LNP + j * WB + ww]);
-                    wout[(size_t)n2 * NN + ww] = sum;
-                }
-            }
-        }
-        cplx<T>* t = Pb;
-        Pb = Qb;
-        Qb = t;
+        for (int t = 0; t < BPT; ++t) wprev[t] = wv[t];
+        wout_prev = wout;
+        Rb = Pb;
+        Pb = Pb == buf0 + 2 * NN * LNP ? buf0 : Pb + NN * LNP;
         bb = bn;
         i = in;
+    }
+    if (pending) {
+        __syncthreads();
+        bside_sum(Rb, wprev, wout_prev);
     }
     if (bact) {
         cplx<T>* out = Wpart + ((size_t)s * nout + jl) * B.ng + plane_off;
@@ -1029,7 +1042,7 @@ void launch_pass3s(const PairBatch& B, const cplx<T>* X, cplx<T>* Wpart, cplx<T>
     if constexpr (NN > 0) {
         using C = P3S<T, NN>;
         const unsigned grid = (unsigned)((size_t)NN * (NN / C::WB) * B.splits);
-        const size_t lds = 2 * sizeof(cplx<T>) * NN * C::LNP;
+        const size_t lds = 3 * sizeof(cplx<T>) * NN * C::LNP;
         hipLaunchKernelGGL((pass3s_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, X, Wpart, W, tw);
     }
 }
