@@ -88,7 +88,7 @@ def pass_kernel_names(info, precision):
         p2 = f"pass2s_kernel<{t}, {n}>" if n else f"pass2_kernel<{t}, 0>"
     if reg & 4:
         p3 = f"pass3r_kernel<{t}, {n}, 8>"
-    elif n and t == "float" and nout <= 8:
+    elif n and nout <= 8:
         p3 = f"pass3s_kernel<{t}, {n}>"
     elif n and nout <= 16:
         p3 = f"pass3f_kernel<{t}, {n}, {jc}>"

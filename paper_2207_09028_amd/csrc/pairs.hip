@@ -805,7 +805,8 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
 // product) is formed.  Three LDS buffers rotate between summed pairs, so that the
 // b-side sum over a pair's partner orbitals is read one pair later, behind the
 // next pair's only barrier: per pair one barrier and 2 LDS accesses per point,
-// against six barriers and 6 accesses in pass3f_kernel.  Used for complex64.
+// against six barriers and 6 accesses in pass3f_kernel.  The column block is 128
+// bytes wide (16 complex64 or 8 complex128 columns).
 template <typename T, int NN>
 struct P3S {
     static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
@@ -1130,13 +1131,9 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
     if constexpr (std::is_same_v<T, float>)
         if ((B.regfft & REGFFT_PASS3) && B.nout <= 8) return launch_pass3_reg(B, X, psi, Wpart, W, s);
     const int nnv = specialised(B);
-    // complex64 only: the complex128 form needs ~200 VGPRs and half the resident waves,
-    // which made it slower than pass3f_kernel
-    if constexpr (std::is_same_v<T, float>) {
-        if (nnv > 0 && B.nout <= 8) {
-            OCCRIK_DISPATCH(nnv, (launch_pass3s<T, NN>(B, X, Wpart, W, tw, s)));
-            return hipGetLastError();
-        }
+    if (nnv > 0 && B.nout <= 8) {
+        OCCRIK_DISPATCH(nnv, (launch_pass3s<T, NN>(B, X, Wpart, W, tw, s)));
+        return hipGetLastError();
     }
     if (nnv > 0 && B.nout <= 16) {
         const int wb = colblock(nnv, (int)sizeof(cplx<T>));
