@@ -39,6 +39,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------
+// streaming store of a pair spectrum: the stored spectra of a batch far exceed the
+// caches and are read back only by the next pass
+template <typename T>
+__device__ __forceinline__ void store_nt(cplx<T>* p, cplx<T> v) {
+    typedef T nv2 __attribute__((ext_vector_type(2)));
+    nv2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<nv2*>(p));
+}
+
 template <typename T, int NN>
 __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const cplx<T>* __restrict__ psi,
                                                             cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
@@ -100,7 +109,7 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
                                                              cplx<T>* __restrict__ X,
                                                              const cplx<T>* __restrict__ twg) {
     using C = P1G<NN>;
-    constexpr int R0 = C::R0, R1 = C::R1, S = C::S, NT = C::NT;
+    constexpr int R0 = C::R0, R1 = C::R1, S = C::S;
     constexpr int PLANE = NN * NN;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -179,7 +188,7 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
             stage_b<T, NN, -1>(u, w);
             cplx<T>* out = X + (size_t)slot * B.ng + (size_t)n1 * PLANE + (size_t)bl * NN + bj;
 #pragma unroll
-            for (int r = 0; r < R1; ++r) out[r * R0] = u[r];
+            for (int r = 0; r < R1; ++r) store_nt<T>(out + r * R0, u[r]);
         }
     }
 }
@@ -499,7 +508,7 @@ __global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T
             stage_b<T, NN, +1>(u, w);
             cplx<T>* dst = X + (size_t)slot * B.ng + (size_t)m2i * NN + bl;
 #pragma unroll
-            for (int r = 0; r < R1; ++r) dst[(size_t)(bj + r * R0) * rs] = u[r];
+            for (int r = 0; r < R1; ++r) store_nt<T>(dst + (size_t)(bj + r * R0) * rs, u[r]);
         }
         cplx<T>* t = Pb;
         Pb = Qb;
