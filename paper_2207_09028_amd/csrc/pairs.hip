@@ -39,8 +39,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------
-// streaming store of a pair spectrum: the stored spectra of a batch far exceed the
-// caches and are read back only by the next pass
+// streaming load and store of a pair spectrum: the stored spectra of a batch far
+// exceed the caches, and each pass touches a stored element once
+template <typename T>
+__device__ __forceinline__ cplx<T> load_nt(const cplx<T>* p) {
+    typedef T nv2 __attribute__((ext_vector_type(2)));
+    const nv2 t = __builtin_nontemporal_load(reinterpret_cast<const nv2*>(p));
+    return mk<T>(t.x, t.y);
+}
+
 template <typename T>
 __device__ __forceinline__ void store_nt(cplx<T>* p, cplx<T> v) {
     typedef T nv2 __attribute__((ext_vector_type(2)));
@@ -435,7 +442,7 @@ __global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T
     auto load_slab = [&](int sl) {
         const cplx<T>* src = X + (size_t)sl * B.ng + (size_t)m2i * NN + al;
 #pragma unroll
-        for (int r = 0; r < R0; ++r) xn[r] = ha ? src[(size_t)(aj + r * R1) * rs] : mk<T>(T(0), T(0));
+        for (int r = 0; r < R0; ++r) xn[r] = ha ? load_nt<T>(src + (size_t)(aj + r * R1) * rs) : mk<T>(T(0), T(0));
     };
     load_slab(s0);
     cplx<T>* Pb = buf0;
@@ -875,7 +882,7 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         bool cj;
         const cplx<T>* src = X + (size_t)(active ? slot_of(bb, i, cj) : 0) * B.ng + plane_off;
 #pragma unroll
-        for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? src[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
+        for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? load_nt<T>(src + (size_t)(sj + r * R1) * NN) : mk<T>(T(0), T(0));
     };
     // stage B rows n2 = sj + r R0: twiddles, the a-side partner orbital (held) and the sums
     const bool bact = hb && active;
