@@ -916,7 +916,7 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
                 const int n2 = e / WB, ww = e - n2 * WB;
                 cplx<T> sum = wv_in[t];
                 for (int j = 0; j < nocc; ++j) sum = cadd<T>(sum, Sb[n2 * LNP + j * WB + ww]);
-                dst[(size_t)n2 * NN + ww] = sum;
+                store_nt<T>(dst + (size_t)n2 * NN + ww, sum);
             }
         }
     };
@@ -937,14 +937,14 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         const cplx<T>* ui_src = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
         cplx<T> ui[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) ui[r] = bact ? ui_src[(size_t)(sj + r * R0) * NN] : mk<T>(T(0), T(0));
+        for (int r = 0; r < R1; ++r) ui[r] = bact ? load_nt<T>(ui_src + (size_t)(sj + r * R0) * NN) : mk<T>(T(0), T(0));
         cplx<T>* wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
         cplx<T> wv[BPT];
 #pragma unroll
         for (int t = 0; t < BPT; ++t) {
             const int e = tid + t * NT;
             const int n2 = e / WB, ww = e - n2 * WB;
-            wv[t] = bside && e < BP ? wout[(size_t)n2 * NN + ww] : mk<T>(T(0), T(0));
+            wv[t] = bside && e < BP ? load_nt<T>(wout + (size_t)n2 * NN + ww) : mk<T>(T(0), T(0));
         }
         __syncthreads();
         if (pending) bside_sum(Rb, wprev, wout_prev);
