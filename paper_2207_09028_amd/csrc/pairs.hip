@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
     const cplx<T>* pi = psi + ((size_t)b * B.kstride + i) * B.ng + poff;
     cplx<T> ui[R0], xn[R0];
 #pragma unroll
-    for (int r = 0; r < R0; ++r) ui[r] = ha ? pi[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
+    for (int r = 0; r < R0; ++r) ui[r] = ha ? load_nt<T>(pi + (size_t)(sj + r * R1) * NN) : mk<T>(T(0), T(0));
     auto load_partner = [&](int j) {
         const cplx<T>* pj = static_cast<const cplx<T>*>(B.outp) + (size_t)j * B.ng + poff;
 #pragma unroll
