@@ -93,6 +93,81 @@ def test_collocation_matches_scalar_bloch_sum():
         assert abs(chi[k, mu, n] - tot) < 1e-11
 
 
+# eq. occmo in the streamed form that writes the paper-sized stored values: chi is
+# formed for a slab of grid points at a time and contracted with C at once.  Pinned
+# against the composition of the two pinned functions above (collocation, then
+# occmo) on whole, ragged and one-point slabs, and against scalar Bloch sums
+# contracted with C by hand at sampled points (independent of ``collocate``).
+
+def _streamed_reference():
+    prob = W.small_problem(kmesh=(2, 2, 1), grid=(6, 5, 4), nocc=2, counts=(1, 1, 1), amin=0.4, amax=2.0)
+    C = W.random_coefficients(prob)
+    chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, 1e-12)
+    return prob, C, occrik.occupied_orbitals(chi, C)
+
+
+def _scalar_orbital(prob, C, k, i, n, n_img=9):
+    lat = prob.cell.lattice
+    kc = olat.kpoints_cartesian(lat, prob.kmesh)[k]
+    r = olat.grid_points(lat, prob.grid)[n]
+    centers = prob.cell.atoms_frac @ lat
+    tot = 0j
+    for mu, (s, ic) in enumerate(collocation.ao_labels(prob.basis)):
+        a, b, c = collocation.cartesian_powers(int(prob.basis.shell_l[s]))[ic]
+        alpha = float(prob.basis.shell_exp[s])
+        R = centers[prob.basis.shell_atom[s]]
+        chi = 0j
+        for t1 in range(-n_img, n_img + 1):
+            for t2 in range(-n_img, n_img + 1):
+                for t3 in range(-n_img, n_img + 1):
+                    T = t1 * lat[0] + t2 * lat[1] + t3 * lat[2]
+                    x = r - R - T
+                    chi += np.exp(1j * kc @ T) * _phi_scalar(x[0], x[1], x[2], alpha, a, b, c)
+        tot += C[k, mu, i] * chi
+    return tot
+
+
+def _check_streamed(prob, C, ref, chunk):
+    psi = collocation.occupied_orbitals_streamed(prob.cell, prob.basis, prob.kmesh, prob.grid, C, 1e-12,
+                                                 chunk=chunk)
+    assert psi.shape == ref.shape
+    assert np.max(np.abs(psi - ref)) <= 1e-13 * np.max(np.abs(ref))
+    return psi
+
+
+@pytest.mark.parametrize("chunk", [7, 1, 1000])
+def test_streamed_orbitals_equal_collocation_then_occmo(chunk):
+    """chunk 7: slabs smaller than the 120-point grid with a one-point last slab;
+    chunk 1: one point per slab; chunk 1000: the whole grid in one slab."""
+    prob, C, ref = _streamed_reference()
+    _check_streamed(prob, C, ref, chunk)
+
+
+def test_streamed_orbitals_match_scalar_bloch_sums():
+    prob, C, _ = _streamed_reference()
+    psi = collocation.occupied_orbitals_streamed(prob.cell, prob.basis, prob.kmesh, prob.grid, C, 1e-12, chunk=7)
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        k, i, n = int(rng.integers(prob.nk)), int(rng.integers(prob.nocc)), int(rng.integers(prob.ng))
+        assert abs(psi[k, i, n] - _scalar_orbital(prob, C, k, i, n)) < 1e-11
+
+
+def test_mutation_streamed_orbitals_without_bloch_phase_fail(monkeypatch):
+    prob, C, ref = _streamed_reference()        # reference from the unmutated path
+    orig = olat.kpoints_fractional
+    monkeypatch.setattr(collocation.lat_mod, "kpoints_fractional", lambda km: 0.0 * orig(km))
+    with pytest.raises(AssertionError):
+        _check_streamed(prob, C, ref, 7)
+
+
+def test_mutation_streamed_orbitals_with_transposed_coefficients_fail():
+    prob, C, ref = _streamed_reference()
+    Ct = C.copy()
+    Ct[:, :2, :] = C[:, :2, :][:, ::-1, :]       # two AO rows exchanged: a wrong mu index
+    with pytest.raises(AssertionError):
+        _check_streamed(prob, Ct, ref, 7)
+
+
 def test_isolated_gto_is_normalised():
     """int |phi|^2 = 1 for s, p, d, f components, by quadrature in a large cell."""
     cell = W.cubic_cell(14.0, [(0.5, 0.5, 0.5)])
