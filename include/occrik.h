@@ -166,7 +166,9 @@ typedef struct {
                                      columns (K~ C_p equals the conventional K C_p for every
                                      column), E_x is the occupied trace.  0 = ground state. */
     int32_t contract_chunks;      /* grid chunks of the contraction's FP64 partial sums, 1..64;
-                                     0 = chosen by the plan (N_g / 4096, clamped) */
+                                     0 = chosen by the plan (N_g / 4096, clamped).  Chunks hold
+                                     whole multiples of 16 points, so the plan keeps only the
+                                     chunks that hold grid points (occrik_plan_info reports it) */
 } occrik_params;
 
 typedef struct occrik_plan occrik_plan;
@@ -361,6 +363,23 @@ occrik_status occrik_get_profile(occrik_plan *plan, occrik_profile *out, int32_t
  *   which = 2: W~   [N_k][nocc + nvir][N_g], e^{-ik.r} W_{j k}(r) of the last build
  * bytes must equal the size of that array in complex128. */
 occrik_status occrik_copy_intermediate(occrik_plan *plan, int32_t which, void *dst, size_t bytes);
+
+/* HBM bandwidth probe (measurement, not part of the paper): a plain streaming kernel
+ * over a buffer of a known size, timed with HIP events on `stream` (NULL = default
+ * stream) on the calling thread's current device.  It sets the achievable rates that
+ * the pair passes are measured against: pass 1 mostly writes, pass 3 mostly reads,
+ * pass 2 reads and writes equal amounts.
+ *   kind         0: read `bytes` of src (dst receives at most 4 bytes, almost never)
+ *                1: write `bytes` to dst
+ *                2: copy `bytes` from src to dst
+ *   width        bytes per lane access, 8 or 16
+ *   nontemporal  1: streaming (non-temporal) loads and stores, as the pair passes use
+ *   dst, src     device buffers of at least `bytes`, aligned to `width`; src unused by kind 1
+ *   reps         timed repetitions after one untimed one
+ *   ms_per_rep   host double: receives the mean milliseconds of one repetition
+ * Synchronous.  OCCRIK_ERR_INVALID_ARG for a bad kind, width, size or alignment. */
+occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t nontemporal, void *dst, const void *src,
+                               size_t bytes, int32_t reps, void *stream, double *ms_per_rep);
 
 const char *occrik_status_string(occrik_status s);
 const char *occrik_last_error_message(void);

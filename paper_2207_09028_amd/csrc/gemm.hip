@@ -387,6 +387,15 @@ int contract_chunk(int ng, int nchunks) {
     return (chunk + 15) / 16 * 16;
 }
 
+// chunks that hold grid points when nchunks are asked for: rounding the chunk up to
+// 16 points can leave trailing chunks empty (12 x 10 x 9 points in 64 chunks of 32
+// fill only 34).  contract_chunk(ng, contract_chunk_count(ng, n)) equals
+// contract_chunk(ng, n), so the chunk boundaries do not move.
+int contract_chunk_count(int ng, int nchunks) {
+    const int chunk = contract_chunk(ng, nchunks);
+    return (ng + chunk - 1) / chunk;
+}
+
 template <typename T>
 hipError_t launch_contract_part(const cplx<T>* chi, size_t ldc, int chi_n0, const cplx<T>* W, double2* Kpart, int nk,
                                 int nao, int nocc, int ng, int nchunks, int c0, int nc, int mode, hipStream_t s) {

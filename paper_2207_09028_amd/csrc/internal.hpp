@@ -103,6 +103,8 @@ hipError_t launch_orbitals(const cplx<T>* chi, size_t ldc, const double2* C, cpl
                            int ng, int n0, int cnt, int mode, hipStream_t s);
 // grid points per partial sum of the contraction
 int contract_chunk(int ng, int nchunks);
+// chunks of contract_chunk(ng, nchunks) points that hold grid points (<= nchunks)
+int contract_chunk_count(int ng, int nchunks);
 // FP64 partial sums Kpart[k][mu][j][c] for chunks c in [c0, c0 + nc) of the grid
 // (nchunks chunks of contract_chunk points); chi holds the points from chi_n0 on,
 // rows of stride ldc

@@ -926,7 +926,10 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     P->kbatch_max = P->kbatch;
     P->splits = splits_for(P, P->kbatch);
     P->group = nout;
-    P->nchunks = params->contract_chunks > 0 ? params->contract_chunks : std::max(1, std::min(64, ng / 4096));
+    // every chunk holds grid points: the integral-direct contraction launches only the
+    // chunks a collocation chunk covers, so an empty trailing chunk would never be written
+    P->nchunks = contract_chunk_count(
+        ng, params->contract_chunks > 0 ? params->contract_chunks : std::max(1, std::min(64, ng / 4096)));
     const size_t max_groups = (size_t)P->kbatch * ((nocc * nout + P->group - 1) / P->group) +
                               (nocc * (nocc + 1) / 2 + P->group - 1) / P->group;
 
@@ -1163,7 +1166,8 @@ occrik_status occrik_plan_autotune(occrik_plan* P, const void* dC, occrik_tune_i
         if (!P->direct && P->params.contract_chunks == 0) {
             const int n0 = P->nchunks;
             int chosen = n0;
-            for (int nc : {std::min(kMaxContractChunks, 2 * n0), std::max(1, n0 / 2)}) {
+            for (int nc : {contract_chunk_count(P->ng, std::min(kMaxContractChunks, 2 * n0)),
+                           contract_chunk_count(P->ng, std::max(1, n0 / 2))}) {
                 if (nc == n0 || nc == chosen || !ensure_chunks(nc)) continue;
                 P->nchunks = nc;
                 if ((st = timed(ms)) != OCCRIK_OK) break;

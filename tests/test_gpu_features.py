@@ -114,6 +114,29 @@ def test_autograd_function_backward():
     assert abs(float(w.grad) - 3.0 * ref["dEx_domega"]) < 1e-10 * abs(3.0 * ref["dEx_domega"])
 
 
+def test_autograd_backward_after_another_forward_on_the_same_plan_raises():
+    """The adjoint reads the plan's last build: a second forward on the same plan before
+    the first backward would hand C1 the gradient of C2, so backward refuses; one plan
+    per live graph gives both gradients."""
+    prob = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.35)
+    prob2 = W.small_problem(kernel=W.KERNEL_ERF_LR, omega=0.35, seed=6)   # same cell, other coefficients
+    C1 = W.random_coefficients(prob)
+    C2 = W.random_coefficients(prob2)
+    plan = Plan(PlanSpec.from_problem(prob))
+    t1 = torch.from_numpy(C1).to("cuda").requires_grad_(True)
+    t2 = torch.from_numpy(C2).to("cuda").requires_grad_(True)
+    E = exchange_energy(plan, t1) + exchange_energy(plan, t2)
+    with pytest.raises(RuntimeError, match="built again"):
+        E.backward()
+    other = Plan(PlanSpec.from_problem(prob))
+    t1.grad = None
+    t2.grad = None
+    E = exchange_energy(plan, t1) + exchange_energy(other, t2)
+    E.backward()
+    assert rel(t1.grad.cpu().numpy(), occrik.energy_gradient_C(ref_for(prob, C1)["Kmi"], prob.nk)) < 1e-10
+    assert rel(t2.grad.cpu().numpy(), occrik.energy_gradient_C(ref_for(prob2, C2)["Kmi"], prob.nk)) < 1e-10
+
+
 def test_grad_before_build_is_a_state_error():
     prob = W.small_problem()
     plan = Plan(PlanSpec.from_problem(prob))
@@ -273,6 +296,28 @@ def test_integral_direct_is_bitwise_the_stored_build(precision):
         assert torch.equal(a[key], b[key]), key
     with pytest.raises(pkg.OccrikError):
         direct.intermediate("chi")
+
+
+@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT])
+def test_integral_direct_with_more_chunks_than_filled_is_bitwise_the_stored_build(precision):
+    """64 contraction chunks asked for on 12 x 10 x 9 points: chunks of 32 points fill
+    only 34 of them, and the plan keeps those 34 (an empty trailing chunk would never be
+    written by the direct contraction, which launches the chunks a collocation chunk
+    covers).  Direct and stored builds stay bitwise equal, and both match the oracle."""
+    prob = W.small_problem(kmesh=(2, 1, 2), grid=(12, 10, 9), nocc=3, seed=41)
+    Cn = W.random_coefficients(prob)
+    C = torch.from_numpy(Cn).to("cuda")
+    stored = Plan(PlanSpec.from_problem(prob, precision=precision, contract_chunks=64))
+    direct = Plan(PlanSpec.from_problem(prob, precision=precision, contract_chunks=64, flags=pkg.FLAG_DIRECT))
+    assert stored.query().contract_chunks == 34 and direct.query().contract_chunks == 34
+    for _ in range(2):
+        a = stored.build(C)
+        b = direct.build(C)
+        for key in ("K", "Kmi", "Ex"):
+            assert torch.equal(a[key], b[key]), key
+    ref = occrik.build(prob, Cn, nyquist="symmetric")
+    tol = 1e-10 * abs(ref["Ex"]) if precision == pkg.PREC_FP64 else 1e-6
+    assert abs(float(b["Ex"][0]) - ref["Ex"]) < tol
 
 
 def test_integral_direct_switches_on_by_memory_budget_with_several_chunks():
