@@ -2,7 +2,9 @@
 
 Forward: occrik_build_device gives E_x (and K_{mu j}).  Backward: occrik_grad
 gives dL/dC = g (2/N_k) K_{mu j} and dL/domega = g dE_x/domega; the potentials
-are recomputed in the omega sweep, never stored.
+are recomputed in the omega sweep, never stored.  The adjoint reads the plan's last
+build, so backward raises if the plan has been built again (or its omega changed)
+since this forward: keep one plan per live graph, or run backward first.
 """
 from __future__ import annotations
 
@@ -20,12 +22,17 @@ class ExchangeEnergy(torch.autograd.Function):
         plan.build_device(C.detach().contiguous(), None, None, Ex)
         plan.status()
         ctx.plan = plan
+        ctx.generation = plan.generation
         ctx.omega_is_tensor = isinstance(omega, torch.Tensor)
         return Ex[0]
 
     @staticmethod
     def backward(ctx, g):
         plan = ctx.plan
+        if plan.generation != ctx.generation:
+            raise RuntimeError("exchange_energy backward: the plan was built again (or its omega changed) after "
+                               "this forward, so it no longer holds the K_{mu j} and orbitals of this forward; "
+                               "use one plan per live graph or call backward before the next build")
         want_w = ctx.omega_is_tensor and ctx.needs_input_grad[1]
         gC, gw = plan.grad(float(g.detach().cpu()), want_C=ctx.needs_input_grad[0], want_omega=want_w)
         gw_t = torch.tensor(gw, dtype=torch.float64) if want_w else None

@@ -93,6 +93,10 @@ class Plan:
         self.nk, self.nao, self.nocc, self.ng = self.info.nk, self.info.nao, self.info.nocc, self.info.ng
         self.nvir = self.info.nvir
         self.ncol = self.nocc + self.nvir        # columns of C, K_{mu j}, psi~ and W~
+        # bumped by every call that replaces the state occrik_grad reads (the last
+        # build's K_{mu j} and orbitals, and omega), so that an adjoint can tell whether
+        # the plan still holds the build it belongs to
+        self.generation = 0
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -123,6 +127,7 @@ class Plan:
 
     def set_omega(self, omega: float):
         check(self._lib.occrik_set_omega(self._h, float(omega)))
+        self.generation += 1
 
     # -- builds ---------------------------------------------------------------
     def _check_C(self, C):
@@ -142,6 +147,7 @@ class Plan:
             raise ValueError("Ex must be one float64 on the plan's device")
         self._sync_stream()
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self.generation += 1
         check(self._lib.occrik_build_device(self._h, ptr(C), ptr(K), ptr(Kmi), ptr(Ex)), self._h)
 
     def status(self):
@@ -164,6 +170,7 @@ class Plan:
         self._check_C(C)
         self._sync_stream()
         ti = _lib.TuneInfo()
+        self.generation += 1
         check(self._lib.occrik_plan_autotune(self._h, ctypes.c_void_p(C.data_ptr()), ctypes.byref(ti)), self._h)
         self.info = self.query()
         return dict(kbatch=ti.kbatch, reg_fft=ti.reg_fft, contract_chunks=ti.contract_chunks, builds=ti.builds,
@@ -202,6 +209,7 @@ class Plan:
         Ex = ctypes.c_double(0.0)
         p = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
         self._sync_stream()
+        self.generation += 1
         check(self._lib.occrik_build(self._h, p(C), p(K), p(Kmi), ctypes.byref(Ex)), self._h)
         return dict(K=K, Kmi=Kmi, Ex=Ex.value)
 
@@ -246,6 +254,8 @@ def build_batch(plans, Cs, Ks=None, Kmis=None, Exs=None):
     arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x.data_ptr()) if x is not None else None for x in xs])
     hp = (_lib.PlanP * n)(*[p._h for p in plans])
     none = [None] * n
+    for p in plans:
+        p.generation += 1
     st = lib.occrik_build_batch(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none))
     check(st)
 
@@ -266,11 +276,15 @@ class BatchGraph:
         none = [None] * n
         self._keep = (plans, Cs, Ks, Kmis, Exs)
         self._h = ctypes.c_void_p()
+        for p in plans:
+            p.generation += 1
         check(lib.occrik_batch_create(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none),
                                       ctypes.byref(self._h)))
         self._lib = lib
 
     def launch(self):
+        for p in self._keep[0]:
+            p.generation += 1
         check(self._lib.occrik_batch_launch(self._h))
 
     def close(self):
