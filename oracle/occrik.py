@@ -20,16 +20,35 @@ index j, the summed k-point is k1 with occupied index i.
   K~ = K_mu (K_ij)^-1 K_mu^H, computed through the Cholesky factor of -K_ij.
 
 Pair momenta are never wrapped: q = k2 - k1 from fractional k-points in [0, 1).
-FFT index order is numpy's (the even-N Nyquist bin is -N/2).  ``nyquist`` =
+FFT index order is numpy's (the even-N Nyquist bin is -N/2).  The DFTs are
+scipy.fft's (pocketfft, the same unnormalised definition as numpy.fft), run over
+the stack of pair densities with ``FFT_WORKERS`` threads: the host's cores, or
+OMP_NUM_THREADS when that is set.  ``nyquist`` =
 "symmetric" replaces f on the Nyquist planes by the mean of f at G_m + q and at
 the mirror index whose Nyquist components are +N/2 (the only change between the
 two modes).
 """
+import os
+
 import numpy as np
+import scipy.fft
 
 from . import collocation
 from . import kernels
 from . import lattice as lat_mod
+
+
+FFT_WORKERS = max(1, int(os.environ.get("OMP_NUM_THREADS") or 0) or (os.cpu_count() or 1))
+
+
+def _dft3(u):
+    """Unnormalised forward DFT over the last three axes."""
+    return scipy.fft.fftn(u, axes=(-3, -2, -1), workers=FFT_WORKERS)
+
+
+def _idft3(u):
+    """Inverse DFT over the last three axes, with the 1/N_g of numpy's convention."""
+    return scipy.fft.ifftn(u, axes=(-3, -2, -1), workers=FFT_WORKERS)
 
 
 class Geometry:
@@ -104,10 +123,10 @@ def pair_potentials(geo, rho, k2, k1, kind, omega, nyquist="fftfreq", want_parse
     ph = np.exp(-1j * (geo.r @ qc))                          # e^{-i q.r}
     shape = rho.shape[:-1] + geo.grid
     u = (rho * ph).reshape(shape)
-    uhat = np.fft.fftn(u, axes=(-3, -2, -1))                 # unnormalised DFT
+    uhat = _dft3(u)                                          # unnormalised DFT
     v = geo.kernel_on_grid(k2, k1, kind, omega, nyquist)
     Z = uhat / geo.ng                                        # Z^G
-    Vt = np.fft.ifftn(v * Z, axes=(-3, -2, -1)) * geo.ng     # sum_G V^G e^{iG.r}
+    Vt = _idft3(v * Z) * geo.ng                              # sum_G V^G e^{iG.r}
     V = Vt.reshape(rho.shape) * np.conj(ph)                  # times e^{iq.r}
     if not want_parseval:
         return V, None
@@ -145,7 +164,7 @@ def exchange_w(geo, psi, out_k, kind, omega, nyquist="fftfreq", parseval=False, 
                 if domega and occ_pair:
                     qc = geo.kcart[k2] - geo.kcart[k1]
                     ph = np.exp(-1j * (geo.r @ qc))
-                    uhat = np.fft.fftn((rho * ph).reshape((nsum,) + geo.grid), axes=(-3, -2, -1))
+                    uhat = _dft3((rho * ph).reshape((nsum,) + geo.grid))
                     dv = geo.kernel_on_grid(k2, k1, kind, omega, nyquist, derivative=True)
                     pd += float(np.sum(dv * np.abs(uhat) ** 2))
     return W, ps, pd
