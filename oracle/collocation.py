@@ -123,10 +123,12 @@ def ao_labels(basis):
     return out
 
 
-def occupied_orbitals_streamed(cell, basis, kmesh, grid, C, tol=1e-12, chunk=1024):
+def occupied_orbitals_streamed(cell, basis, kmesh, grid, C, tol=1e-12, chunk=1024, points=None):
     """psi[k, i, n] = sum_mu C[k, mu, i] chi[k, mu, n] (paper eq. occmo) without
     holding chi for every k: chi is formed for a slab of grid points at a time
-    (the same Bloch sums as ``collocate``) and contracted with C at once."""
+    (the same Bloch sums as ``collocate``) and contracted with C at once.
+    ``points`` = (n0, n1) restricts the work to the grid points n0 <= n < n1 (psi
+    stays zero elsewhere); it is used only to time a bounded sample."""
     lattice = cell.lattice
     kf = lat_mod.kpoints_fractional(kmesh)
     r = lat_mod.grid_points(lattice, grid)
@@ -143,8 +145,9 @@ def occupied_orbitals_streamed(cell, basis, kmesh, grid, C, tol=1e-12, chunk=102
         powers = cartesian_powers(l)
         shells.append((l, alpha, R, t @ lattice, np.exp(2j * np.pi * (kf @ t.T)), powers,
                        [component_norm(alpha, *p) for p in powers]))
-    for n0 in range(0, ng, chunk):
-        rc = r[n0:n0 + chunk]
+    p0, p1 = (0, ng) if points is None else (int(points[0]), min(ng, int(points[1])))
+    for n0 in range(p0, p1, chunk):
+        rc = r[n0:min(n0 + chunk, p1)]
         chi = np.empty((nk, nao, rc.shape[0]), dtype=np.complex128)
         mu0 = 0
         for (l, alpha, R, T, phase, powers, norms) in shells:
@@ -154,5 +157,5 @@ def occupied_orbitals_streamed(cell, basis, kmesh, grid, C, tol=1e-12, chunk=102
                 phi = norms[ic] * x[..., 0] ** a * x[..., 1] ** b * x[..., 2] ** c * radial
                 chi[:, mu0 + ic, :] = phase @ phi
             mu0 += len(powers)
-        psi[:, :, n0:n0 + chunk] = np.matmul(C.transpose(0, 2, 1), chi)
+        psi[:, :, n0:n0 + rc.shape[0]] = np.matmul(C.transpose(0, 2, 1), chi)
     return psi
