@@ -1,12 +1,15 @@
 """Write the stored oracle results used by the GPU parity tests at full workload sizes.
 
-    python tests/golden/make_golden.py [prec] [diff] [paper]
+    python tests/golden/make_golden.py [prec] [diff] [batch] [paper]
 
 Calls only ``oracle`` (and the seeded ``workloads`` generators); nothing here
 comes from the GPU library.  Outputs (numpy .npz, no pickles):
 
   prec.npz   full build of the 3x3x3 k, 100 AO, 36^3 workload (symmetric Nyquist)
   diff.npz   full build of the 4x4x4 k, 200 AO, 40^3 long-range workload with dE_x/domega
+  batch.npz  full builds of the eight capped cells of the ragged batch
+             (workloads.batch_parity_problems): per cell i, Kmi_i, Kij_i, Ex_i and
+             the rows Krows_i of K~ at the k-points Kk_i
   paper.npz  the 6x6x6 k, 350 AO, 48^3 workload sampled on two output k-points
              (Gamma and k index 43): K_{mu j}(k), K_ij(k), the per-k energy terms
              and every ninth row of the assembled K~(k); every sampled quantity
@@ -44,6 +47,20 @@ def full(name, domega=False):
     print(name, "Ex", res["Ex"], "seconds", out["seconds"], flush=True)
 
 
+def batch():
+    out = {}
+    t0 = time.time()
+    for i, prob in enumerate(W.batch_parity_problems()):
+        C = W.random_coefficients(prob)
+        res = occrik.build(prob, C, nyquist="symmetric")
+        ks = np.array([0, prob.nk - 1])
+        rows = np.arange(0, prob.nao, max(1, prob.nao // 8))
+        out.update({f"Kmi_{i}": res["Kmi"], f"Kij_{i}": res["Kij"], f"Ex_{i}": res["Ex"],
+                    f"Kk_{i}": ks, f"Krows_{i}": rows, f"K_{i}": res["K"][ks][:, rows]})
+        print(prob.name, "Ex", res["Ex"], "seconds", time.time() - t0, flush=True)
+    np.savez_compressed(os.path.join(HERE, "batch.npz"), **out)
+
+
 def paper():
     prob = W.make_problem("paper")
     C = W.random_coefficients(prob)
@@ -68,11 +85,13 @@ def paper():
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["prec", "diff", "paper"]
+    which = sys.argv[1:] or ["prec", "diff", "batch", "paper"]
     for w in which:
         if w == "prec":
             full("prec")
         elif w == "diff":
             full("diff", domega=True)
+        elif w == "batch":
+            batch()
         elif w == "paper":
             paper()

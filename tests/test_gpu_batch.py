@@ -1,0 +1,85 @@
+"""The ragged batch (a parallel loop of Alg. 3 over independent cells) against the FP64
+oracle: eight capped cells of the batch workload, FP64 and FP32-split members, every
+plan autotuned, run as one concurrent batch and as a replayed HIP graph.
+
+Expected values are ``tests/golden/batch.npz``, written by ``tests/golden/make_golden.py``
+from the oracle alone.  Bars: FP64 1e-10 relative (max-norm over each array, relative
+energies); FP32-split |dE_x| <= 1e-6 Eh, max |dK~| <= 1e-5 and max |dK_{mu j}| <= 1e-5.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import occrik
+import paper_2207_09028_amd as pkg
+from paper_2207_09028_amd.plan import BatchGraph, Plan, PlanSpec, build_batch
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch.npz")
+TOL64 = 1e-10
+EX_TOL_REDUCED = 1e-6
+K_TOL_REDUCED = 1e-5
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _check(i, prob, C, prec, g, K, Kmi, Ex, tag):
+    K, Kmi, Ex = K.cpu().numpy(), Kmi.cpu().numpy(), float(Ex.cpu()[0])
+    ks, rows = g[f"Kk_{i}"], g[f"Krows_{i}"]
+    Ks = K[ks][:, rows]
+    Kij = occrik.occupied_block(C, Kmi)
+    ref_ex = float(g[f"Ex_{i}"])
+    if prec == pkg.PREC_FP64:
+        assert rel(Kmi, g[f"Kmi_{i}"]) < TOL64, (tag, prob.name)
+        assert rel(Kij, g[f"Kij_{i}"]) < TOL64, (tag, prob.name)
+        assert rel(Ks, g[f"K_{i}"]) < TOL64, (tag, prob.name)
+        assert abs(Ex - ref_ex) < TOL64 * abs(ref_ex), (tag, prob.name)
+    else:
+        assert np.max(np.abs(Kmi - g[f"Kmi_{i}"])) <= K_TOL_REDUCED, (tag, prob.name)
+        assert np.max(np.abs(Ks - g[f"K_{i}"])) <= K_TOL_REDUCED, (tag, prob.name)
+        assert abs(Ex - ref_ex) <= EX_TOL_REDUCED, (tag, prob.name)
+
+
+def test_ragged_batch_against_the_oracle():
+    if not os.path.exists(GOLDEN):
+        pytest.skip(f"{GOLDEN} not generated")
+    g = np.load(GOLDEN)
+    probs = W.batch_parity_problems()
+    precs = [pkg.PREC_FP32_SPLIT if i % 2 == 0 else pkg.PREC_FP64 for i in range(len(probs))]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plans, Cn, Cs, Ks, Kmis, Es = [], [], [], [], [], []
+        for prob, prec in zip(probs, precs):
+            C = W.random_coefficients(prob)
+            plan = Plan(PlanSpec.from_problem(prob, precision=prec))
+            Ct = torch.from_numpy(C).to("cuda")
+            plan.autotune(Ct)
+            plans.append(plan)
+            Cn.append(C)
+            Cs.append(Ct)
+            Ks.append(torch.empty((plan.nk, plan.nao, plan.nao), dtype=torch.complex128, device="cuda"))
+            Kmis.append(torch.empty((plan.nk, plan.nao, plan.ncol), dtype=torch.complex128, device="cuda"))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        build_batch(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es)
+        side.synchronize()
+        for i, prob in enumerate(probs):
+            plans[i].status()
+            _check(i, prob, Cn[i], precs[i], g, Ks[i], Kmis[i], Es[i], "eager")
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es)
+        for rep in range(2):
+            for t in Ks + Kmis + Es:
+                t.fill_(float("nan"))
+            x = torch.randn(1 << 20, device="cuda")
+            (x * x).sum().item()                       # unrelated eager work between replays
+            graph.launch()
+            side.synchronize()
+            for i, prob in enumerate(probs):
+                plans[i].status()
+                _check(i, prob, Cn[i], precs[i], g, Ks[i], Kmis[i], Es[i], f"graph replay {rep}")
+        graph.close()

@@ -71,9 +71,17 @@ def test_full_workload_fp32_split(name):
     g = golden(name)
     prob = W.make_problem(name)
     C = W.random_coefficients(prob)
-    _, out = gpu_build(prob, C, pkg.PREC_FP32_SPLIT)
+    plan, out = gpu_build(prob, C, pkg.PREC_FP32_SPLIT)
     assert abs(out["Ex"][0] - float(g["Ex"])) <= EX_TOL_REDUCED
     assert np.max(np.abs(out["K"][:2] - g["K_sample"])) <= K_TOL_REDUCED
+    assert np.max(np.abs(out["Kmi"] - g["Kmi"])) <= K_TOL_REDUCED
+    if "dEx_domega" in g.files:
+        # the adjoint of the reduced-precision forward (FP64 reductions): dE_x/dC =
+        # (2/N_k) K_{mu j} (from eq. exxao) at the K bar, dE_x/domega within 1e-5 relative
+        gC, dw = plan.grad(want_C=True, want_omega=True)
+        ref = occrik.energy_gradient_C(g["Kmi"], prob.nk)
+        assert np.max(np.abs(gC.cpu().numpy() - ref)) <= (2.0 / prob.nk) * K_TOL_REDUCED
+        assert abs(dw - float(g["dEx_domega"])) <= 1e-5 * abs(float(g["dEx_domega"]))
 
 
 @pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT])

@@ -34,6 +34,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field, replace
 from typing import List, Sequence, Tuple
 
+
 import numpy as np
 
 BOHR_PER_ANGSTROM = 1.0 / 0.529177210903
@@ -258,6 +259,26 @@ def batch_problems(n: int = 64, seed: int = 1000) -> List[Problem]:
         nocc = int(rng.integers(4, 9))
         out.append(Problem(f"batch{c}", Cell(lat, np.array(atoms, dtype=float)), basis, (m, m, m), (g, g, g),
                            nocc, seed=seed + 7919 * (c + 1)))
+    return out
+
+
+def batch_parity_problems() -> List[Problem]:
+    """Eight cells of the ragged batch (``batch_problems``) for parity against the FP64
+    oracle: their cells, bases (51-350 AOs) and occupied counts (4-8), with the k-mesh
+    and grid capped so that the oracle builds all eight in a few minutes.  Grids: the
+    compiled sizes 24^3, 30^3 and 32^3 and the run-time sizes 27 x 25 x 20 and 20^3;
+    k-meshes 2^3 and one 3^3."""
+    full = batch_problems()
+    picks = [(57, None, None), (8, None, None), (34, None, None), (55, None, None), (44, None, None),
+             (51, (27, 25, 20), None), (16, (20, 20, 20), None), (43, None, (2, 2, 2))]
+    out = []
+    for idx, grid, kmesh in picks:
+        p = full[idx]
+        if grid is not None:
+            p = replace(p, grid=grid)
+        if kmesh is not None:
+            p = replace(p, kmesh=kmesh)
+        out.append(p)
     return out
 
 
