@@ -308,6 +308,19 @@ occrik_status occrik_plan_status(occrik_plan *plan);
 /* k index of the last OCCRIK_ERR_NOT_PD, or -1. */
 int32_t occrik_last_error_k(const occrik_plan *plan);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses that forbid
+ * hipMalloc): occrik_build with the same arguments, results and errors, but staged
+ * through a static 64 MiB device array of the library (one per device, held until the
+ * process ends) instead of per-call hipMalloc/hipFree.  C and K_{mu j} are staged whole
+ * and K~ a group of k-points at a time, so 2 N_k N_ao (nocc + nvir) 16 bytes (rounded up
+ * to 256-byte blocks) plus, when K is requested, N_ao^2 16 bytes for one k-point must fit:
+ * larger plans get OCCRIK_ERR_INVALID_ARG (use occrik_build).  The plan's own workspaces,
+ * allocated by occrik_plan_create, are used as by every build; this call allocates
+ * nothing.  Profiling must be off (OCCRIK_ERR_STATE otherwise).  Every call on a device
+ * shares that device's staging array: calls that overlap on one device (plans on
+ * different streams or threads) race and must be serialised by the caller.  Synchronous. */
+occrik_status occrik_build_static(occrik_plan *plan, const double *C, double *K, double *Kmi, double *Ex);
+
 /* Gradients of E_x after a build on this plan (not part of the paper; the
  * adjoint of the build).  With gEx = dL/dE_x:
  *   dgradC     [N_k][N_ao][nocc + nvir] complex128 device buffer (or NULL) receives

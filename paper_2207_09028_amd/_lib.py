@@ -83,6 +83,7 @@ SIGNATURES = {
     "occrik_set_omega": (c_int32, [PlanP, c_double]),
     "occrik_build": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
     "occrik_build_device": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "occrik_build_static": (c_int32, [PlanP, c_void_p, c_void_p, c_void_p, c_void_p]),
     "occrik_conventional_k": (c_int32, [PlanP, c_int32, c_void_p, c_void_p, c_void_p]),
     "occrik_plan_autotune": (c_int32, [PlanP, c_void_p, ctypes.POINTER(TuneInfo)]),
     "occrik_plan_status": (c_int32, [PlanP]),

@@ -23,6 +23,10 @@
 
 using namespace occrik;
 
+// Staging area of occrik_build_static (see below): 64 MiB per device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -61,6 +65,15 @@ struct DeviceGuard {
 constexpr int kConvGroup = 8;
 // largest number of grid chunks of the contraction's partial sums
 constexpr int kMaxContractChunks = 64;
+
+// Staging area of occrik_build_static, for callers that cannot allocate device memory:
+// one file-scope array per device, held until the process ends.  Host code never
+// passes `scratch` itself to the runtime (on the host it is only a stand-in symbol);
+// it uses the device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device on the first call there.
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
 
 struct ProfileEvents {
     hipEvent_t e[5];
@@ -1261,6 +1274,64 @@ occrik_status occrik_build(occrik_plan* P, const double* C, double* K, double* K
     if (dKmi) (void)hipFree(dKmi);
     if (dEx) (void)hipFree(dEx);
     return st;
+}
+
+occrik_status occrik_build_static(occrik_plan* P, const double* C, double* K, double* Kmi, double* Ex) {
+    if (!P || !C) return fail(OCCRIK_ERR_INVALID_ARG, "null plan or C");
+    if (P->profiling) return fail(OCCRIK_ERR_STATE, "occrik_build_static needs profiling off (it creates events)");
+    if (P->device < 0 || P->device >= kMaxStaticDevices)
+        return fail(OCCRIK_ERR_UNSUPPORTED, "occrik_build_static: device ordinal beyond the staging table");
+    DeviceGuard guard(P->device);
+    const size_t nC = (size_t)P->nk * P->nao * P->nout * 2;
+    for (size_t i = 0; i < nC; ++i)
+        if (!std::isfinite(C[i])) return fail(OCCRIK_ERR_NONFINITE, "non-finite entries in C");
+    // staging layout: C | K_{mu j} | E_x | K~ of as many k-points as fit
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t bC = nC * sizeof(double);
+    const size_t offKmi = up(bC), offEx = up(offKmi + bC), offK = up(offEx + sizeof(double));
+    const size_t perK = (size_t)P->nao * P->nao * sizeof(double2);
+    if (offK > kStaticScratchBytes || (K && offK + perK > kStaticScratchBytes))
+        return fail(OCCRIK_ERR_INVALID_ARG,
+                    "occrik_build_static: C, K_{mu j} and one k-point of K~ need " +
+                        std::to_string(offK + (K ? perK : 0)) + " bytes of staging, more than the " +
+                        std::to_string(kStaticScratchBytes) + " it holds (use occrik_build)");
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (!g_static_ptr[P->device]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(e, "occrik_build_static: hipGetSymbolAddress");
+            if (!p) return fail(OCCRIK_ERR_DEVICE, "occrik_build_static: no device address for the staging area");
+            g_static_ptr[P->device] = p;
+        }
+        base = static_cast<char*>(g_static_ptr[P->device]);
+    }
+    hipStream_t s = P->stream;
+    double2* sC = reinterpret_cast<double2*>(base);
+    double2* sKmi = reinterpret_cast<double2*>(base + offKmi);
+    double* sEx = reinterpret_cast<double*>(base + offEx);
+    double2* sK = reinterpret_cast<double2*>(base + offK);
+    OCCRIK_HIP(hipMemcpyAsync(sC, C, bC, hipMemcpyHostToDevice, s));
+    occrik_status st = occrik_build_device(P, sC, nullptr, Kmi ? sKmi : nullptr, Ex ? sEx : nullptr);
+    if (st == OCCRIK_OK) st = occrik_plan_status(P);
+    if (st != OCCRIK_OK) return st;
+    if (Kmi) OCCRIK_HIP(hipMemcpyAsync(Kmi, sKmi, bC, hipMemcpyDeviceToHost, s));
+    if (Ex) OCCRIK_HIP(hipMemcpyAsync(Ex, sEx, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (K) {
+        // K~ = -xi xi^H in groups of k-points that fit the staging area, each copied out
+        // before the next group overwrites it (same stream)
+        const int nkc = (int)std::min<size_t>((size_t)P->nk, (kStaticScratchBytes - offK) / perK);
+        OCCRIK_HIP(launch_xi(P->Kmi, P->L, P->Y, P->flags, P->nk, P->nao, P->nout, s));
+        for (int k0 = 0; k0 < P->nk; k0 += nkc) {
+            const int n = std::min(nkc, P->nk - k0);
+            OCCRIK_HIP(launch_ktilde(P->Y + (size_t)k0 * P->nao * P->nout, sK, P->flags, n, P->nao, P->nout, s));
+            OCCRIK_HIP(hipMemcpyAsync(K + (size_t)k0 * P->nao * P->nao * 2, sK, (size_t)n * perK,
+                                      hipMemcpyDeviceToHost, s));
+        }
+    }
+    OCCRIK_HIP(hipStreamSynchronize(s));
+    return OCCRIK_OK;
 }
 
 occrik_status occrik_grad(occrik_plan* P, double gEx, void* dgradC, double* dgradOmega) {

@@ -213,6 +213,21 @@ class Plan:
         check(self._lib.occrik_build(self._h, p(C), p(K), p(Kmi), ctypes.byref(Ex)), self._h)
         return dict(K=K, Kmi=Kmi, Ex=Ex.value)
 
+    def build_host_static(self, C: np.ndarray, want_K=True, want_Kmi=True):
+        """occrik_build_static: occrik_build staged through the library's static device
+        array (no device allocation per call); synchronous, host arrays in and out."""
+        C = np.ascontiguousarray(C, dtype=np.complex128)
+        if C.shape != (self.nk, self.nao, self.ncol):
+            raise ValueError("bad C shape")
+        K = np.empty((self.nk, self.nao, self.nao), np.complex128) if want_K else None
+        Kmi = np.empty((self.nk, self.nao, self.ncol), np.complex128) if want_Kmi else None
+        Ex = ctypes.c_double(0.0)
+        p = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
+        self._sync_stream()
+        self.generation += 1
+        check(self._lib.occrik_build_static(self._h, p(C), p(K), p(Kmi), ctypes.byref(Ex)), self._h)
+        return dict(K=K, Kmi=Kmi, Ex=Ex.value)
+
     def grad(self, gEx=1.0, want_C=True, want_omega=False):
         """occrik_grad after a build: dL/dC (device tensor) and dL/domega (float)."""
         g = torch.empty((self.nk, self.nao, self.ncol), dtype=torch.complex128, device=self.device) if want_C else None
