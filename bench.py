@@ -119,27 +119,135 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(prob, nblocks, seed=0):
-    """Time the FP64 oracle's Alg. 3 inner loops on a bounded sample of the same workload."""
+def cpu_baseline(prob, nblocks, slab=2048, seed=0):
+    """The FP64 oracle, as it stands, on the host's cores, timed phase by phase on bounded
+    samples of the same workload, each scaled to one whole build by its own count:
+      orbitals     collocation and eq. occmo for every k on `slab` grid points (x N_g / slab)
+      pair loops   Alg. 3 inner loops for one output k-point over `nblocks` summed k-points
+                   (x N_k^2 / nblocks; the oracle loops over every ordered block)
+      contraction  K_{mu j} of one output k-point (x N_k)
+    The FFTs run on the oracle's FFT_WORKERS threads, its pointwise numpy work on one."""
+    import platform
+
     import numpy as np
-    from oracle import occrik
+
+    import workloads as W
+    from oracle import collocation, occrik
     geo = occrik.Geometry(prob.cell, prob.kmesh, prob.grid)
+    C = W.random_coefficients(prob)
+    t0 = time.perf_counter()
+    collocation.occupied_orbitals_streamed(prob.cell, prob.basis, prob.kmesh, prob.grid, C, prob.lattice_tol,
+                                           chunk=1024, points=(0, slab))
+    t_orb = time.perf_counter() - t0
+    # orbitals of the summed k-points for the loops: synthetic values of the right shape
+    # (the loops' cost does not depend on the values)
     rng = np.random.default_rng(seed)
+    ks = list(range(nblocks))
     psi = np.zeros((geo.nk, prob.nocc, geo.ng), dtype=np.complex128)
-    ks = [0] + list(range(1, nblocks))
-    for k in set(ks):
+    for k in ks:
         psi[k] = rng.standard_normal((prob.nocc, geo.ng)) + 1j * rng.standard_normal((prob.nocc, geo.ng))
     t0 = time.perf_counter()
-    occrik.exchange_w(geo, psi, [0], prob.kernel, prob.omega, "symmetric", k1_subset=ks)
-    dt = time.perf_counter() - t0
-    per_block = dt / len(ks)
-    full = per_block * geo.nk * geo.nk
-    return dict(value=1.0 / full, unit="builds/s", cores=1, kind="oracle",
-                sample=(f"oracle Alg. 3 inner loops for 1 output k-point x {len(ks)} summed k-points "
-                        f"({len(ks) * prob.nocc ** 2} pair round trips at {prob.grid[0]}^3, FP64 numpy FFT, "
-                        f"synthetic orbitals) in {dt:.1f} s; builds/s extrapolated by the "
-                        f"{geo.nk}x{geo.nk}/{len(ks)} block ratio (collocation and contractions excluded)"),
-                seconds_sample=dt)
+    Wk, _, _ = occrik.exchange_w(geo, psi, [0], prob.kernel, prob.omega, "symmetric", k1_subset=ks)
+    t_pairs = time.perf_counter() - t0
+    chi = rng.standard_normal((1, prob.nao, geo.ng)) + 1j * rng.standard_normal((1, prob.nao, geo.ng))
+    t0 = time.perf_counter()
+    occrik.contract(geo, chi, Wk)
+    t_con = time.perf_counter() - t0
+    full_orb = t_orb * geo.ng / slab
+    full_pairs = t_pairs * geo.nk * geo.nk / nblocks
+    full_con = t_con * geo.nk
+    full = full_orb + full_pairs + full_con
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    sample = t_orb + t_pairs + t_con
+    return dict(value=1.0 / full, unit="builds/s", cores=occrik.FFT_WORKERS, kind="oracle",
+                sample=(f"FP64 oracle on {occrik.FFT_WORKERS} threads (scipy.fft workers; numpy pointwise work "
+                        f"on one) of {os.cpu_count()} host CPUs ({cpu}): orbitals (collocation + eq. occmo, all "
+                        f"{geo.nk} k) on {slab} of {geo.ng} grid points {t_orb:.1f} s; Alg. 3 loops for 1 output "
+                        f"k-point x {nblocks} summed k-points ({nblocks * prob.nocc ** 2} pair round trips, "
+                        f"synthetic orbitals) {t_pairs:.1f} s; contraction of 1 output k-point {t_con:.1f} s; "
+                        f"scaled to one build: orbitals x{geo.ng / slab:.0f} = {full_orb:.0f} s, loops "
+                        f"x{geo.nk * geo.nk / nblocks:.0f} = {full_pairs:.0f} s, contraction x{geo.nk} = "
+                        f"{full_con:.0f} s (assembly excluded: {geo.nk} Cholesky solves of {prob.nocc}x{prob.nocc})"),
+                seconds_sample=sample, host_cpus=os.cpu_count(), host_cpu_model=cpu,
+                seconds_per_build=dict(orbitals=full_orb, pair_loops=full_pairs, contraction=full_con))
+
+
+def build_bytes(nk, nao, nocc, ng, elem, reuse=True):
+    """Algorithmic HBM bytes of one build (streaming model): every stored pair's round trip
+    moves its spectrum through device memory four times (pass 1 writes, pass 2 reads and
+    writes, pass 3 reads); every (k, k') block reads the orbitals of both k-points and
+    updates W (read and write) of the output side, and of the summed side too when the
+    conjugate pair is reused; the two grid contractions stream the Bloch AOs once each."""
+    blk = nocc * ng * elem
+    if reuse:
+        pairs = nk * (nk - 1) // 2 * nocc * nocc + nk * nocc * (nocc + 1) // 2
+        blocks = nk * (nk - 1) // 2 * 6 * blk + nk * 3 * blk
+    else:
+        pairs = nk * nk * nocc * nocc
+        blocks = nk * nk * 4 * blk
+    return pairs * 4 * ng * elem + blocks + 2 * nk * nao * ng * elem
+
+
+def build_roofline(prob, r, mode):
+    elem = 16 if mode == "fp64" else 8
+    b = build_bytes(prob.nk, prob.nao, prob.nocc, prob.ng, elem)
+    achieved = b / (r["ms_per_build"] * 1e-3) / 1e9
+    return {"algorithmic_bytes": b, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "ms_per_build": r["ms_per_build"]}
+
+
+def dominant_kernel(r):
+    """The pair pass with the largest accumulated time in the timed builds: its algorithmic
+    bytes per launch over its mean launch time from the plan's HIP events."""
+    prof = r["profile"]
+    q = max(range(3), key=lambda i: prof["ms_pass"][i])
+    nl = max(1, prof["launches_pass"][q])
+    avg_ms = prof["ms_pass"][q] / nl
+    bytes_per_launch = prof["bytes_pass"][q] / nl
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": r["pass_kernels"][q], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": avg_ms,
+            "bytes_per_launch": bytes_per_launch}
+
+
+def max_cond_kij(C, Kmi):
+    """Largest 2-norm condition number over k of the occupied block K_ij = C^H K_{mu j}
+    (the matrix whose Cholesky factor the assembly uses)."""
+    import numpy as np
+    kmi = Kmi.cpu().numpy()
+    kij = np.einsum("kmi,kmj->kij", np.conj(C), kmi)
+    return float(np.max(np.linalg.cond(kij)))
+
+
+def hbm_probe_rates(gib: float = 2.0, reps: int = 5):
+    """Achievable read-only, write-only and copy rates from the library's probe kernels
+    (16-byte lanes; streaming loads for the read, temporal stores for the write, streaming
+    accesses for the copy: the fastest forms measured)."""
+    import ctypes
+
+    import torch
+
+    from paper_2207_09028_amd import _lib
+    lib = _lib.load()
+    nbytes = int(gib * (1 << 30)) // 16 * 16
+    a = torch.zeros(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.zeros_like(a)
+    torch.cuda.synchronize()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {}
+    for name, kind, nt in (("read_gbs", 0, 1), ("write_gbs", 1, 0), ("copy_gbs", 2, 1)):
+        ms = ctypes.c_double()
+        _lib.check(lib.occrik_hbm_probe(kind, 16, nt, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                        nbytes, reps, stream, ctypes.byref(ms)))
+        out[name] = round(nbytes * (2 if kind == 2 else 1) / (ms.value * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_bandwidth(gib: float = 2.0, reps: int = 5) -> float:
@@ -170,8 +278,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--modes", default="fp64,fp32,fp32split")
     ap.add_argument("--profile-level", type=int, default=2)
-    ap.add_argument("--cpu-blocks", type=int, default=64)
+    ap.add_argument("--cpu-blocks", type=int, default=64, help="summed k-points of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch timing")
+    ap.add_argument("--batch-cells", type=int, default=64)
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: the exchange build runs on a single MI355X and "
@@ -195,6 +305,7 @@ def main(argv=None):
         log(f"[bench] mode {m}: plan + {a.warmup} warmup + {a.steps} timed builds")
         r, K, Kmi = run_mode(prob, C_dev, prec[m], NYQUIST_SYMMETRIC, a.steps, a.warmup, a.profile_level,
                              keep_K=True)
+        r["cond_Kij_max"] = max_cond_kij(C, Kmi)
         if m == "fp64":
             K_ref, Kmi_ref = K, Kmi
         elif K_ref is not None:
@@ -215,20 +326,31 @@ def main(argv=None):
     if not valid:
         head = "fp64"
     hr = results[head]
-    prof = hr["profile"]
-    # dominant pair kernel: the pass with the largest accumulated time
-    q = max(range(3), key=lambda i: prof["ms_pass"][i])
-    nl = max(1, prof["launches_pass"][q])
-    avg_ms = prof["ms_pass"][q] / nl
-    bytes_per_launch = prof["bytes_pass"][q] / nl
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    kname = hr["pass_kernels"][q]
+    probe = hbm_probe_rates()
     copy_gbs = copy_bandwidth()
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kname), "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch,
-                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
-    log(f"[bench] device copy {copy_gbs:.0f} GB/s; {kname} {achieved:.0f} GB/s")
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s; probe read {probe['read_gbs']:.0f}, write "
+        f"{probe['write_gbs']:.0f}, copy {probe['copy_gbs']:.0f} GB/s")
+    roofline = dominant_kernel(hr)
+    roofline.update({"traffic": measured_traffic(roofline["kernel"]), "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(roofline["achieved"] / copy_gbs, 4), "probe_gbs": probe,
+                     "build": build_roofline(prob, hr, head)})
+    log(f"[bench] {roofline['kernel']} {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of peak); build "
+        f"{roofline['build']['achieved']:.0f} GB/s ({roofline['build']['frac']:.3f})")
+    others = {}
+    for m, r in results.items():
+        if m != head:
+            o = dominant_kernel(r)
+            o["build"] = build_roofline(prob, r, m)
+            others[m] = o
+    roofline["other_modes"] = others
+    batch = None
+    if not a.no_batch:
+        from paper_2207_09028_amd.sweep import time_batch
+        log(f"[bench] ragged batch: {a.batch_cells} cells, FP32, plans + serial / concurrent / graph")
+        batch = time_batch(W.batch_problems(a.batch_cells), PREC_FP32, reps=3)
+        batch["workload"] = (f"{a.batch_cells} seeded cells (fcc/bcc/rocksalt, 1-4 atoms, 50-350 AO, 4-8 occ, "
+                             f"2^3-4^3 k, 24^3-48^3 grids), Coulomb, FP32, Bloch AOs stored")
+        log(f"[bench] ragged batch: graph {batch['ms_graph']:.1f} ms = {batch['builds_per_s_graph']:.1f} builds/s")
     cpu = None
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle sample of {a.cpu_blocks} blocks")
@@ -245,6 +367,7 @@ def main(argv=None):
                    "mode": head, "accuracy_gate_met": valid},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
         "modes": {m: {k: v for k, v in r.items() if k != "profile"} | {"ms_pass": r["profile"]["ms_pass"],
                                                                         "launches_pass": r["profile"]["launches_pass"]}
                   for m, r in results.items()},
