@@ -242,8 +242,8 @@ def hbm_probe_rates(gib: float = 2.0, reps: int = 5):
     out = {}
     for name, kind, nt in (("read_gbs", 0, 1), ("write_gbs", 1, 0), ("copy_gbs", 2, 1)):
         ms = ctypes.c_double()
-        _lib.check(lib.occrik_hbm_probe(kind, 16, nt, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()),
-                                        nbytes, reps, stream, ctypes.byref(ms)))
+        _lib.check(lib.occrik_hbm_probe(kind, 16, nt, 0, ctypes.c_void_p(b.data_ptr()),
+                                        ctypes.c_void_p(a.data_ptr()), nbytes, reps, stream, ctypes.byref(ms)))
         out[name] = round(nbytes * (2 if kind == 2 else 1) / (ms.value * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()

@@ -380,19 +380,22 @@ occrik_status occrik_copy_intermediate(occrik_plan *plan, int32_t which, void *d
 /* HBM bandwidth probe (measurement, not part of the paper): a plain streaming kernel
  * over a buffer of a known size, timed with HIP events on `stream` (NULL = default
  * stream) on the calling thread's current device.  It sets the achievable rates that
- * the pair passes are measured against: pass 1 mostly writes, pass 3 mostly reads,
- * pass 2 reads and writes equal amounts.
+ * the pair passes are measured against: pass 1 mostly writes (with one read for about
+ * eight writes), pass 3 mostly reads, pass 2 reads and writes equal amounts.
  *   kind         0: read `bytes` of src (dst receives at most 4 bytes, almost never)
  *                1: write `bytes` to dst
  *                2: copy `bytes` from src to dst
+ *                3: write `bytes` to dst and read one access of src for every
+ *                   `read_every` written (src needs bytes / read_every)
  *   width        bytes per lane access, 8 or 16
  *   nontemporal  1: streaming (non-temporal) loads and stores, as the pair passes use
+ *   read_every   kind 3 only (>= 1); ignored otherwise
  *   dst, src     device buffers of at least `bytes`, aligned to `width`; src unused by kind 1
  *   reps         timed repetitions after one untimed one
  *   ms_per_rep   host double: receives the mean milliseconds of one repetition
- * Synchronous.  OCCRIK_ERR_INVALID_ARG for a bad kind, width, size or alignment. */
-occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t nontemporal, void *dst, const void *src,
-                               size_t bytes, int32_t reps, void *stream, double *ms_per_rep);
+ * Synchronous.  OCCRIK_ERR_INVALID_ARG for a bad kind, width, size, ratio or alignment. */
+occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t nontemporal, int32_t read_every, void *dst,
+                               const void *src, size_t bytes, int32_t reps, void *stream, double *ms_per_rep);
 
 const char *occrik_status_string(occrik_status s);
 const char *occrik_last_error_message(void);

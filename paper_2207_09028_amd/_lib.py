@@ -99,8 +99,8 @@ SIGNATURES = {
     "occrik_set_profiling": (c_int32, [PlanP, c_int32]),
     "occrik_get_profile": (c_int32, [PlanP, ctypes.POINTER(Profile), c_int32]),
     "occrik_copy_intermediate": (c_int32, [PlanP, c_int32, c_void_p, c_size_t]),
-    "occrik_hbm_probe": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_int32, c_void_p,
-                                   ctypes.POINTER(c_double)]),
+    "occrik_hbm_probe": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_int32,
+                                   c_void_p, ctypes.POINTER(c_double)]),
     "occrik_status_string": (ctypes.c_char_p, [c_int32]),
     "occrik_last_error_message": (ctypes.c_char_p, []),
     "occrik_grid_size_supported": (c_int32, [c_int32]),

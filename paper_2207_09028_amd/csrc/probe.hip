@@ -1,5 +1,5 @@
 // HBM bandwidth probes: plain streaming kernels of a known size.  Their times
-// give the achievable read-only, write-only and copy rates of the device, the
+// give the achievable read-only, write-only, copy and mixed rates of the device, the
 // denominators beside the 8 TB/s spec figure that the pair passes (pass 1
 // mostly writes, pass 3 mostly reads, pass 2 reads and writes in equal parts)
 // are measured against, and their FETCH_SIZE / WRITE_SIZE counters calibrate
@@ -92,9 +92,35 @@ __global__ void __launch_bounds__(kProbeThreads) probe_copy(const V* __restrict_
     for (; i < n; i += stride) st<V, NT>(dst + i, ld<V, NT>(src + i));
 }
 
+// kind 3: write n vectors and read one vector of src for every `every` written (src
+// holds n / every vectors): a write stream with a share of reads, like pass 1
 template <typename V, bool NT>
-hipError_t launch_probe(int kind, void* dst, const void* src, size_t n, int grid, hipStream_t s) {
-    if (kind == 0) {
+__global__ void __launch_bounds__(kProbeThreads) probe_mixed(const V* __restrict__ src, V* __restrict__ dst,
+                                                             size_t n, int every, uint32_t sentinel,
+                                                             uint32_t* __restrict__ sink) {
+    const size_t stride = (size_t)gridDim.x * kProbeThreads;
+    uint32_t acc = 0;
+    size_t k = 0;
+    for (size_t i = (size_t)blockIdx.x * kProbeThreads + threadIdx.x; i < n; i += stride, ++k) {
+        V v;
+        v.x = (uint32_t)i;
+        v.y = (uint32_t)(i >> 32);
+        if constexpr (sizeof(V) == 16) {
+            v.z = v.x;
+            v.w = v.y;
+        }
+        st<V, NT>(dst + i, v);
+        if (k % every == 0) acc ^= fold(ld<V, NT>(src + i / every));
+    }
+    if (acc == sentinel) sink[0] = acc;
+}
+
+template <typename V, bool NT>
+hipError_t launch_probe(int kind, int every, void* dst, const void* src, size_t n, int grid, hipStream_t s) {
+    if (kind == 3) {
+        hipLaunchKernelGGL((probe_mixed<V, NT>), dim3(grid), dim3(kProbeThreads), 0, s, static_cast<const V*>(src),
+                           static_cast<V*>(dst), n, every, 0x9e3779b9u, static_cast<uint32_t*>(dst));
+    } else if (kind == 0) {
         hipLaunchKernelGGL((probe_read<V, NT>), dim3(grid), dim3(kProbeThreads), 0, s, static_cast<const V*>(src), n,
                            0x9e3779b9u, static_cast<uint32_t*>(dst));
     } else if (kind == 1) {
@@ -108,11 +134,11 @@ hipError_t launch_probe(int kind, void* dst, const void* src, size_t n, int grid
 
 }  // namespace
 
-extern "C" occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t nontemporal, void* dst,
-                                          const void* src, size_t bytes, int32_t reps, void* stream,
+extern "C" occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t nontemporal, int32_t read_every,
+                                          void* dst, const void* src, size_t bytes, int32_t reps, void* stream,
                                           double* ms_per_rep) {
-    if (kind < 0 || kind > 2 || (width != 8 && width != 16) || reps < 1 || !ms_per_rep || bytes == 0 ||
-        bytes % (size_t)width != 0)
+    if (kind < 0 || kind > 3 || (width != 8 && width != 16) || reps < 1 || !ms_per_rep || bytes == 0 ||
+        bytes % (size_t)width != 0 || (kind == 3 && read_every < 1))
         return OCCRIK_ERR_INVALID_ARG;
     if ((kind != 1 && !src) || !dst) return OCCRIK_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(dst) | (kind != 1 ? reinterpret_cast<uintptr_t>(src) : 0)) % width != 0)
@@ -126,10 +152,10 @@ extern "C" occrik_status occrik_hbm_probe(int32_t kind, int32_t width, int32_t n
     const int grid = ncu * 8;
     auto run = [&]() -> hipError_t {
         if (width == 8)
-            return nontemporal ? launch_probe<u32x2, true>(kind, dst, src, n, grid, s)
-                               : launch_probe<u32x2, false>(kind, dst, src, n, grid, s);
-        return nontemporal ? launch_probe<u32x4, true>(kind, dst, src, n, grid, s)
-                           : launch_probe<u32x4, false>(kind, dst, src, n, grid, s);
+            return nontemporal ? launch_probe<u32x2, true>(kind, read_every, dst, src, n, grid, s)
+                               : launch_probe<u32x2, false>(kind, read_every, dst, src, n, grid, s);
+        return nontemporal ? launch_probe<u32x4, true>(kind, read_every, dst, src, n, grid, s)
+                           : launch_probe<u32x4, false>(kind, read_every, dst, src, n, grid, s);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = run();  // untimed first pass

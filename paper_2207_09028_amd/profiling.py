@@ -70,13 +70,24 @@ def bandwidth(gib: float = 4.0, reps: int = 10):
         for width in (8, 16):
             for nt in (0, 1):
                 ms = ctypes.c_double()
-                _lib.check(lib.occrik_hbm_probe(kind, width, nt, ctypes.c_void_p(b.data_ptr()),
+                _lib.check(lib.occrik_hbm_probe(kind, width, nt, 0, ctypes.c_void_p(b.data_ptr()),
                                                 ctypes.c_void_p(a.data_ptr()), nbytes, reps, stream,
                                                 ctypes.byref(ms)))
                 moved = nbytes * (2 if kind == 2 else 1)
                 gbs = moved / (ms.value * 1e-3) / 1e9
                 out[(names[kind], width, nt)] = gbs
                 print(f"{names[kind]:6s} {width:5d} {nt:3d} {gib:6.2f} {ms.value:9.3f} {gbs:8.1f}", flush=True)
+    # a write stream with one read for every `every` writes (pass 1 reads about one for eight)
+    print(f"\n{'writes per read':>16s} {'nt':>3s} {'write GB/s':>11s} {'read GB/s':>10s} {'total GB/s':>11s}")
+    for every in (64, 16, 8, 4, 2, 1):
+        for nt in (0, 1):
+            ms = ctypes.c_double()
+            _lib.check(lib.occrik_hbm_probe(3, 16, nt, every, ctypes.c_void_p(b.data_ptr()),
+                                            ctypes.c_void_p(a.data_ptr()), nbytes, reps, stream, ctypes.byref(ms)))
+            w = nbytes / (ms.value * 1e-3) / 1e9
+            r = w / every
+            out[("mixed", every, nt)] = w + r
+            print(f"{every:16d} {nt:3d} {w:11.1f} {r:10.1f} {w + r:11.1f}", flush=True)
     return out
 
 

@@ -118,3 +118,14 @@ def test_profile_traffic_reads_as_unmeasured_after_a_change(tmp_path):
     assert sources_sha256("b,a", str(tmp_path)) != h
     (tmp_path / "b").write_bytes(b"launch2")
     assert sources_sha256("a,b", str(tmp_path)) != h
+
+
+def test_hbm_probe_rejects_bad_arguments_before_any_device_work():
+    lib = pkg.load()
+    buf = ctypes.c_void_p(4096)          # never dereferenced: every case fails validation first
+    ms = ctypes.c_double()
+    for kind, width, every, nbytes, reps in [(4, 16, 0, 1024, 1), (-1, 16, 0, 1024, 1), (0, 12, 0, 1024, 1),
+                                            (1, 16, 0, 0, 1), (1, 16, 0, 1000, 1), (1, 16, 0, 1024, 0),
+                                            (3, 16, 0, 1024, 1)]:
+        assert lib.occrik_hbm_probe(kind, width, 0, every, buf, buf, nbytes, reps, None, ctypes.byref(ms)) == 1
+    assert lib.occrik_hbm_probe(0, 16, 0, 0, buf, buf, 1024, 1, None, None) == 1
