@@ -250,6 +250,49 @@ def hbm_probe_rates(gib: float = 2.0, reps: int = 5):
     return out
 
 
+def time_adjoint(name="diff", reps=3):
+    """The differentiation workload (4^3 k, 200 AO, 8 occ, 40^3, long-range erf kernel,
+    omega 0.3): ms of a forward build and of the adjoint, dE_x/dC = (2/N_k) K_{mu j} and
+    dE_x/domega from the forward-only sweep, FP32-split forward with FP64 reductions."""
+    import torch
+
+    import workloads as W
+    from paper_2207_09028_amd import NYQUIST_SYMMETRIC, PREC_FP32_SPLIT
+    from paper_2207_09028_amd.plan import Plan, PlanSpec
+    prob = W.make_problem(name)
+    C = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+    plan = Plan(PlanSpec.from_problem(prob, precision=PREC_FP32_SPLIT, nyquist=NYQUIST_SYMMETRIC))
+    Ex = torch.empty((1,), dtype=torch.float64, device="cuda")
+    Kmi = torch.empty((plan.nk, plan.nao, plan.ncol), dtype=torch.complex128, device="cuda")
+
+    def events(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    ms_build = events(lambda: plan.build_device(C, None, Kmi, Ex))
+    plan.status()
+    ms_grad_c = events(lambda: plan.grad(want_C=True, want_omega=False))
+    t0 = time.perf_counter()
+    _, dw = plan.grad(want_C=False, want_omega=True)
+    ms_grad_w = 1e3 * (time.perf_counter() - t0)
+    out = dict(workload=(f"{name}: diamond fcc 2-atom cell, {prob.nao} AO, {prob.nocc} occ, "
+                         f"{prob.kmesh[0]}x{prob.kmesh[1]}x{prob.kmesh[2]} k, {prob.grid[0]}^3 grid, "
+                         f"erf long-range kernel omega {prob.omega}"),
+               mode="fp32split", ms_build=round(ms_build, 3), ms_grad_C=round(ms_grad_c, 3),
+               ms_grad_omega=round(ms_grad_w, 3), Ex=float(Ex[0]), dEx_domega=dw)
+    plan.close()
+    del C, Ex, Kmi
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(gib: float = 2.0, reps: int = 5) -> float:
     """Achievable HBM bandwidth: a plain 2 GiB device-to-device copy (read + write bytes)
     timed with events, the measured denominator beside the spec-sheet peak."""
@@ -282,6 +325,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch timing")
     ap.add_argument("--batch-cells", type=int, default=64)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: the exchange build runs on a single MI355X and "
@@ -351,6 +395,12 @@ def main(argv=None):
         batch["workload"] = (f"{a.batch_cells} seeded cells (fcc/bcc/rocksalt, 1-4 atoms, 50-350 AO, 4-8 occ, "
                              f"2^3-4^3 k, 24^3-48^3 grids), Coulomb, FP32, Bloch AOs stored")
         log(f"[bench] ragged batch: graph {batch['ms_graph']:.1f} ms = {batch['builds_per_s_graph']:.1f} builds/s")
+    adjoint = None
+    if not a.no_adjoint:
+        log("[bench] adjoint: differentiation workload, FP32-split forward + dE/dC + dE/domega")
+        adjoint = time_adjoint()
+        log(f"[bench] adjoint: build {adjoint['ms_build']:.1f} ms, dE/dC {adjoint['ms_grad_C']:.2f} ms, "
+            f"dE/domega {adjoint['ms_grad_omega']:.1f} ms")
     cpu = None
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle sample of {a.cpu_blocks} blocks")
@@ -368,6 +418,7 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batch": batch,
+        "adjoint": adjoint,
         "modes": {m: {k: v for k, v in r.items() if k != "profile"} | {"ms_pass": r["profile"]["ms_pass"],
                                                                         "launches_pass": r["profile"]["launches_pass"]}
                   for m, r in results.items()},
