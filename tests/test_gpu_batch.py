@@ -83,3 +83,55 @@ def test_ragged_batch_against_the_oracle():
                 plans[i].status()
                 _check(i, prob, Cn[i], precs[i], g, Ks[i], Kmis[i], Es[i], f"graph replay {rep}")
         graph.close()
+
+
+def test_batch_of_mixed_plan_kinds_against_the_oracle():
+    """One graph holding plans of every kind a batch may mix: integral-direct (Alg. 4),
+    conduction bands treated exactly, the truncated Coulomb kernel in FP32-split, and
+    the long-range kernel with the Madelung G + q = 0 term on a compiled grid; each
+    member against the oracle (FP64 1e-10 relative; FP32-split at the reduced bars) on
+    two replays."""
+    from oracle import collocation
+    cases = [
+        (W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=51),
+         dict(flags=pkg.FLAG_DIRECT), dict()),
+        (W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=3, counts=(2, 1, 1), seed=52),
+         dict(nocc=2, nvir=1), dict(nvir=1)),
+        (W.small_problem(kmesh=(2, 2, 1), grid=(16, 15, 12), nocc=3, kernel=W.KERNEL_TRUNC_COULOMB, seed=53),
+         dict(precision=pkg.PREC_FP32_SPLIT), dict()),
+        (W.small_problem(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=4, counts=(2, 1, 1), kernel=W.KERNEL_ERF_LR,
+                         omega=0.35, seed=54),
+         dict(flags=pkg.FLAG_MADELUNG), dict(madelung=True)),
+    ]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plans, Cn, Cs, Ks, Kmis, Es, refs = [], [], [], [], [], [], []
+        for prob, spec_kw, oracle_kw in cases:
+            C = W.random_coefficients(prob)
+            chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+            refs.append(occrik.build(prob, C, chi=chi, nyquist="symmetric", **oracle_kw))
+            plan = Plan(PlanSpec.from_problem(prob, **spec_kw))
+            plans.append(plan)
+            Cn.append(C)
+            Cs.append(torch.from_numpy(C).to("cuda"))
+            Ks.append(torch.empty((plan.nk, plan.nao, plan.nao), dtype=torch.complex128, device="cuda"))
+            Kmis.append(torch.empty((plan.nk, plan.nao, plan.ncol), dtype=torch.complex128, device="cuda"))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        assert plans[0].query().integral_direct == 1 and plans[1].nvir == 1
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es)
+        for rep in range(2):
+            for t in Ks + Kmis + Es:
+                t.fill_(float("nan"))
+            graph.launch()
+            side.synchronize()
+            for i, ((prob, spec_kw, _), ref) in enumerate(zip(cases, refs)):
+                plans[i].status()
+                K, Kmi, Ex = Ks[i].cpu().numpy(), Kmis[i].cpu().numpy(), float(Es[i].cpu()[0])
+                if spec_kw.get("precision") == pkg.PREC_FP32_SPLIT:
+                    assert np.max(np.abs(K - ref["K"])) <= K_TOL_REDUCED, (rep, i)
+                    assert abs(Ex - ref["Ex"]) <= EX_TOL_REDUCED, (rep, i)
+                else:
+                    assert rel(Kmi, ref["Kmi"]) < TOL64, (rep, i)
+                    assert rel(K, ref["K"]) < TOL64, (rep, i)
+                    assert abs(Ex - ref["Ex"]) < TOL64 * abs(ref["Ex"]), (rep, i)
+        graph.close()

@@ -7,7 +7,7 @@ benchmark times (symmetric Nyquist, automatic k batching, register-resident
 transforms on these cubic grids).
 
 Bars: FP64 1e-10 relative (max-norm over each array, relative energies);
-FP32 with split-bf16 contractions |dE_x| <= 1e-6 Eh and max |dK~| <= 1e-5.
+FP32 (plain or with split-bf16 contractions) |dE_x| <= 1e-6 Eh and max |dK~| <= 1e-5.
 """
 import os
 
@@ -66,12 +66,15 @@ def test_full_workload_fp64(name):
         assert abs(dw - float(g["dEx_domega"])) < TOL64 * abs(float(g["dEx_domega"]))
 
 
+@pytest.mark.parametrize("precision", [pkg.PREC_FP32_SPLIT, pkg.PREC_FP32])
 @pytest.mark.parametrize("name", ["prec", "diff"])
-def test_full_workload_fp32_split(name):
+def test_full_workload_reduced_precision(name, precision):
+    """Complex64 transforms with split-bf16 (or plain FP32) contractions and FP64
+    reductions, against the stored FP64 oracle values at the reduced-precision bars."""
     g = golden(name)
     prob = W.make_problem(name)
     C = W.random_coefficients(prob)
-    plan, out = gpu_build(prob, C, pkg.PREC_FP32_SPLIT)
+    plan, out = gpu_build(prob, C, precision)
     assert abs(out["Ex"][0] - float(g["Ex"])) <= EX_TOL_REDUCED
     assert np.max(np.abs(out["K"][:2] - g["K_sample"])) <= K_TOL_REDUCED
     assert np.max(np.abs(out["Kmi"] - g["Kmi"])) <= K_TOL_REDUCED
@@ -84,7 +87,7 @@ def test_full_workload_fp32_split(name):
         assert abs(dw - float(g["dEx_domega"])) <= 1e-5 * abs(float(g["dEx_domega"]))
 
 
-@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT])
+@pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT, pkg.PREC_FP32])
 def test_paper_workload_sampled_kpoints(precision):
     """6x6x6 k, 350 AO, 8 occupied, 48^3: the whole build on the GPU, checked on the
     output k-points the oracle computed exactly (each sums over all 216 k')."""
