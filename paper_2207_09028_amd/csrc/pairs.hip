@@ -900,6 +900,10 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     }
     int bb = B.b0 + q0 / nocc, i = q0 - (q0 / nocc) * nocc;
     if (q0 < q1) load_column(bb, i);
+    // The twiddle and held-orbital loads above sit in branches; without a wait here the
+    // compiler's counter bookkeeping carries them into the loop and has stage B wait for
+    // every load in flight, the next pair's prefetched column included.
+    __builtin_amdgcn_s_waitcnt(0);
     // Pb: this pair's buffer; Rb: the previous pair's, whose b-side products are summed
     // behind this pair's barrier (written before it, rewritten two pairs later, after
     // the barrier that follows the sum)
@@ -925,6 +929,11 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
         const bool bside = B.reuse && !(B.diag && bb == B.a);
         bool cj;
         (void)slot_of(bb, i, cj);
+        // this pair's column and the last pair's W block were loaded a pair ago: one wait
+        // for everything in flight, so that no wait inside the pair covers the loads
+        // issued for the next one (only the summed orbital, loaded below and used in
+        // stage B, is waited for within the pair)
+        __builtin_amdgcn_s_waitcnt(0);
         if (ha) {
             cplx<T> a[R0];
 #pragma unroll
