@@ -1161,21 +1161,16 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
         return hipGetLastError();
     }
     if (nnv > 0 && B.nout <= 16) {
+        // 9-16 output orbitals: 16 orbital lines per column
+        constexpr int JC = 16;
         const int wb = colblock(nnv, (int)sizeof(cplx<T>));
         const unsigned grid = (unsigned)((size_t)nnv * (nnv / wb) * B.splits);
-        const int jc = B.nout <= 8 ? 8 : 16;
         int lnp = 1;
-        while (lnp < jc * wb) lnp *= 2;
+        while (lnp < JC * wb) lnp *= 2;
         const size_t lds = sizeof(cplx<T>) * (3 * kMaxN + (size_t)nnv * lnp);
-        if (jc == 8) {
-            OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 8>), dim3(grid),
-                                                                       dim3(kPass3Threads), lds, s, B, X, Wpart,
-                                                                       W, tw));
-        } else {
-            OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, 16>), dim3(grid),
-                                                                       dim3(kPass3Threads), lds, s, B, X, Wpart,
-                                                                       W, tw));
-        }
+        OCCRIK_DISPATCH(nnv, if constexpr (NN > 0) hipLaunchKernelGGL((pass3f_kernel<T, NN, JC>), dim3(grid),
+                                                                   dim3(kPass3Threads), lds, s, B, X, Wpart, W,
+                                                                   tw));
         return hipGetLastError();
     }
     const int nfull_b = B.reuse ? B.nb - (B.diag ? 1 : 0) : 0;

@@ -356,11 +356,14 @@ def test_degenerate_shapes(case, mode):
 
 
 @pytest.mark.parametrize("nocc,n,kmesh", [(1, 24, (1, 2, 2)), (2, 36, (2, 1, 1)), (7, 32, (1, 1, 2)),
-                                          (6, 40, (1, 2, 1))])
+                                          (6, 40, (1, 2, 1)), (9, 36, (1, 1, 2)), (12, 30, (2, 1, 1)),
+                                          (16, 24, (1, 2, 1))])
 @pytest.mark.parametrize("precision", [pkg.PREC_FP64, pkg.PREC_FP32_SPLIT])
 def test_compiled_sizes_with_other_orbital_counts(nocc, n, kmesh, precision):
     """Rows of the diagonal block with 1..nocc stored pairs, odd and even orbital
-    counts and partial orbital groups in the compiled-size pair passes."""
+    counts and partial orbital groups in the compiled-size pair passes; 9 to 16
+    occupied orbitals (the largest count a plan takes) run pass 3 with 16 orbital
+    lines per column."""
     prob = W.small_problem(kmesh=kmesh, grid=(n, n, n), nocc=nocc, counts=(2, 2, 1), seed=120 + nocc)
     C = W.random_coefficients(prob)
     ref = oracle_result(prob, C, "symmetric")
