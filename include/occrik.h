@@ -346,18 +346,39 @@ occrik_status occrik_build_batch(int32_t n, occrik_plan *const *plans, const voi
 
 /* The same batch recorded once as a HIP graph and replayed by occrik_batch_launch
  * with one launch: for SCF-style loops that rebuild the same cells from the same
- * buffers.  occrik_batch_create runs no device work; it needs the plans on a
+ * buffers.  occrik_batch_create runs no kernels; it needs the plans on a
  * non-default stream and profiling off.  The plans and every buffer passed here
  * must outlive the batch object; each launch reads dC and writes dK/dKmi/dEx as
  * they are at launch time.  After create the plans count as built (occrik_grad and
  * occrik_plan_status then refer to the latest launch).  Launches are asynchronous
- * on the plans' stream; occrik_batch_destroy waits for that stream. */
+ * on the plans' stream; occrik_batch_destroy waits for that stream and frees the
+ * batch's own device memory. */
 typedef struct occrik_batch occrik_batch;
 occrik_status occrik_batch_create(int32_t n, occrik_plan *const *plans, const void *const *dC,
                                   void *const *dK, void *const *dKmi, double *const *dEx,
                                   occrik_batch **out);
 occrik_status occrik_batch_launch(occrik_batch *batch);
 void occrik_batch_destroy(occrik_batch *batch);
+
+/* occrik_batch_create with fused rounds: the loop over (k, k') blocks of Sec. II.D,
+ * Alg. 3, run for several cells at once.  Plans that share the working precision
+ * (complex128 for FP64; complex64 for FP32 and FP32-split), a compiled cubic grid
+ * (24, 30, 32, 36, 40 or 48 points a side), the LDS pair-pass kernels, a kernel-value
+ * cache and the pass-3 form (up to 8, or 9 to 16 output orbitals) form groups of at
+ * least two.  Round r of a group runs the r-th pair-pass launch of each of its plans
+ * as one launch per pass (pass 1, pass 2, pass 3, the W reduction); the groups' rounds
+ * run on the worker streams beside the other plans' whole builds, and the grouped
+ * plans' orbitals and contractions before and after them.  Results are bitwise those
+ * of single builds.  Before recording it allocates and uploads, synchronously, the
+ * rounds' item table (a few hundred bytes per pair-pass launch of each grouped plan),
+ * which occrik_batch_destroy frees.  Same arguments and rules as occrik_batch_create. */
+occrik_status occrik_batch_create_fused(int32_t n, occrik_plan *const *plans, const void *const *dC,
+                                        void *const *dK, void *const *dKmi, double *const *dEx,
+                                        occrik_batch **out);
+/* The number of plans of a recorded batch whose pair passes run in fused rounds
+ * (0 for occrik_batch_create, or when no two plans share a kernel form), written to
+ * *nplans. */
+occrik_status occrik_batch_fused(const occrik_batch *batch, int32_t *nplans);
 
 /* Profiling: level 1 records HIP events around the phases of every build on
  * the plan's stream; level 2 also brackets every pair-pass launch.

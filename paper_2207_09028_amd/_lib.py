@@ -94,8 +94,12 @@ SIGNATURES = {
     "occrik_batch_create": (c_int32, [c_int32, ctypes.POINTER(PlanP), ctypes.POINTER(c_void_p),
                                       ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                       ctypes.POINTER(c_void_p)]),
+    "occrik_batch_create_fused": (c_int32, [c_int32, ctypes.POINTER(PlanP), ctypes.POINTER(c_void_p),
+                                      ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                      ctypes.POINTER(c_void_p)]),
     "occrik_batch_launch": (c_int32, [c_void_p]),
     "occrik_batch_destroy": (None, [c_void_p]),
+    "occrik_batch_fused": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "occrik_set_profiling": (c_int32, [PlanP, c_int32]),
     "occrik_get_profile": (c_int32, [PlanP, ctypes.POINTER(Profile), c_int32]),
     "occrik_copy_intermediate": (c_int32, [PlanP, c_int32, c_void_p, c_size_t]),

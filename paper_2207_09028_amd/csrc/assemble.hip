@@ -43,22 +43,34 @@ __global__ void __launch_bounds__(256) kij_kernel(const double2* __restrict__ C,
                                                   int nocc_e) {
     __shared__ double2 kij[kMaxOccA * kMaxOccA];
     __shared__ double2 l[kMaxOccA * kMaxOccA];
+    __shared__ double2 part[256];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     const double2* Ck = C + (size_t)k * nao * nocc;
     const double2* Kk = Kmi + (size_t)k * nao * nocc;
-    if (t < nocc * nocc) {
-        const int i = t / nocc, j = t - i * nocc;
+    // entry (i, j) = sum_mu conj(C_{mu i}) K_{mu j}: G threads per entry take every G-th
+    // AO, and their G partial sums are added in a fixed order
+    const int nn = nocc * nocc;
+    const int G = nn > 0 ? 256 / nn : 1;
+    if (t < nn * G) {
+        const int e = t / G, g = t - e * G;
+        const int i = e / nocc, j = e - i * nocc;
         double sx = 0.0, sy = 0.0;
-        for (int mu = 0; mu < nao; ++mu) {
+        for (int mu = g; mu < nao; mu += G) {
             const double2 c = Ck[(size_t)mu * nocc + i];
             const double2 v = Kk[(size_t)mu * nocc + j];
             sx += c.x * v.x + c.y * v.y;
             sy += c.x * v.y - c.y * v.x;
         }
-        double2 r;
-        r.x = sx;
-        r.y = sy;
+        part[t] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if (t < nn) {
+        double2 r = make_double2(0.0, 0.0);
+        for (int g = 0; g < G; ++g) {
+            r.x += part[t * G + g].x;
+            r.y += part[t * G + g].y;
+        }
         kij[t] = r;
         Kij[(size_t)k * nocc * nocc + t] = r;
     }

@@ -28,6 +28,8 @@
 // consecutive points of its AO row and of W as 16-byte vectors; MODE 1 issues
 // eight 16x16x4 products for them, MODE 2 the six split-bf16 16x16x32 products.  Both kernels stream the Bloch AOs once and are bandwidth-bound for
 // the few occupied columns involved.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace occrik {
@@ -98,13 +100,13 @@ __device__ __forceinline__ f4 mfma_split(const float* a, const float* b, f4 c) {
 
 constexpr int kMaxRowTiles = 2;   // 2 nocc <= 32
 constexpr int kOrbChunk = 32;     // AOs per LDS chunk of the A operand
-constexpr int kOrbTiles = 4;      // 16-point tiles per wave
+constexpr int kOrbTiles = 4;      // 16-point tiles per wave (one tile when a launch is small)
 constexpr int kFlush = 32;        // FP32 MFMA steps (x4 forms) between FP64 flushes in the contraction
 
 // ---------------------------------------------------------------------------
-// orbitals: one workgroup = 4 waves x 4 tiles x 16 points of one k
+// orbitals: one workgroup = 4 waves x TILES tiles x 16 points of one k
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, int TILES>
 __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__ chi, size_t ldc,
                                                      const double2* __restrict__ C, cplx<T>* __restrict__ psi,
                                                      int nao, int nocc, int ng, int n0, int cnt) {
@@ -113,15 +115,15 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
     __shared__ T alds[kMaxRowTiles][16][KCH];
     const int k = blockIdx.y;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int nbase = (blockIdx.x * 4 + wave) * kOrbTiles * 16;    // point of the chunk
+    const int nbase = (blockIdx.x * 4 + wave) * TILES * 16;    // point of the chunk
     const int rt_n = (2 * nocc + 15) / 16;
     const T* chir = reinterpret_cast<const T*>(chi) + (size_t)2 * k * nao * ldc;
     const double2* Ck = C + (size_t)k * nao * nocc;
-    acc_t acc[kMaxRowTiles][kOrbTiles];
+    acc_t acc[kMaxRowTiles][TILES];
 #pragma unroll
     for (int rt = 0; rt < kMaxRowTiles; ++rt)
 #pragma unroll
-        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = acc_t{};
+        for (int t = 0; t < TILES; ++t) acc[rt][t] = acc_t{};
     for (int m0 = 0; m0 < nao; m0 += kOrbChunk) {
         __syncthreads();
         for (int idx = threadIdx.x; idx < kMaxRowTiles * 16 * KCH; idx += 256) {
@@ -140,9 +142,9 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
             for (int s = 0; s < KCH / 4; ++s) {
                 const int kk = 4 * s + (l >> 4);
                 const int mu = m0 + (kk >> 1), cc = kk & 1;
-                T bv[kOrbTiles];
+                T bv[TILES];
 #pragma unroll
-                for (int t = 0; t < kOrbTiles; ++t) {
+                for (int t = 0; t < TILES; ++t) {
                     const int n = nbase + 16 * t + (l & 15);
                     bv[t] = (mu < nao && n < cnt) ? chir[2 * ((size_t)mu * ldc + n) + cc] : T(0);
                 }
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
                     if (rt < rt_n) {
                         const T a = alds[rt][l & 15][kk];
 #pragma unroll
-                        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = mfma4<MODE>(a, bv[t], acc[rt][t]);
+                        for (int t = 0; t < TILES; ++t) acc[rt][t] = mfma4<MODE>(a, bv[t], acc[rt][t]);
                     }
                 }
             }
@@ -159,9 +161,9 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll 1
             for (int s = 0; s < KCH / 32; ++s) {
                 const int kk0 = 32 * s + 8 * (l >> 4);
-                float bv[kOrbTiles][8];
+                float bv[TILES][8];
 #pragma unroll
-                for (int t = 0; t < kOrbTiles; ++t) {
+                for (int t = 0; t < TILES; ++t) {
                     const int n = nbase + 16 * t + (l & 15);
                     // (re, im) of one AO at this point in one 8-byte load (kk0 is even)
 #pragma unroll
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
 #pragma unroll
                         for (int v = 0; v < 8; ++v) av[v] = (float)alds[rt][l & 15][kk0 + v];
 #pragma unroll
-                        for (int t = 0; t < kOrbTiles; ++t) acc[rt][t] = mfma_split(av, bv[t], acc[rt][t]);
+                        for (int t = 0; t < TILES; ++t) acc[rt][t] = mfma_split(av, bv[t], acc[rt][t]);
                     }
                 }
             }
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(256) orbitals_mfma(const cplx<T>* __restrict__
     for (int rt = 0; rt < kMaxRowTiles; ++rt) {
         if (rt >= rt_n) continue;
 #pragma unroll
-        for (int t = 0; t < kOrbTiles; ++t) {
+        for (int t = 0; t < TILES; ++t) {
             const int n = nbase + 16 * t + (l & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -369,16 +371,28 @@ template <typename T>
 hipError_t launch_orbitals(const cplx<T>* chi, size_t ldc, const double2* C, cplx<T>* psi, int nk, int nao, int nocc,
                            int ng, int n0, int cnt, int mode, hipStream_t s) {
     if (cnt <= 0) return hipSuccess;
-    const int per_wg = 4 * kOrbTiles * 16;
+    // four 16-point tiles per wave share each A-operand load; a launch that would then
+    // hold fewer than 2048 workgroups (a small cell) takes one tile per wave instead, so
+    // that more of the chip streams chi~.  Every point's sum runs in the same order
+    // either way.
+    const bool wide = (size_t)((cnt + 4 * kOrbTiles * 16 - 1) / (4 * kOrbTiles * 16)) * nk >= 2048;
+    const int per_wg = 4 * (wide ? kOrbTiles : 1) * 16;
     dim3 grid((unsigned)((cnt + per_wg - 1) / per_wg), (unsigned)nk);
-    if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((orbitals_mfma<T, 0>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
-    } else {
-        if (mode == 2)
-            hipLaunchKernelGGL((orbitals_mfma<T, 2>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
-        else
-            hipLaunchKernelGGL((orbitals_mfma<T, 1>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0, cnt);
-    }
+    auto go = [&](auto tiles) {
+        constexpr int TL = decltype(tiles)::value;
+        if constexpr (sizeof(T) == 8) {
+            hipLaunchKernelGGL((orbitals_mfma<T, 0, TL>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0,
+                               cnt);
+        } else if (mode == 2) {
+            hipLaunchKernelGGL((orbitals_mfma<T, 2, TL>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0,
+                               cnt);
+        } else {
+            hipLaunchKernelGGL((orbitals_mfma<T, 1, TL>), grid, dim3(256), 0, s, chi, ldc, C, psi, nao, nocc, ng, n0,
+                               cnt);
+        }
+    };
+    if (wide) go(std::integral_constant<int, kOrbTiles>{});
+    else go(std::integral_constant<int, 1>{});
     return hipGetLastError();
 }
 

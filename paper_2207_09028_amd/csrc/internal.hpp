@@ -92,6 +92,34 @@ size_t kcache_tables(int M1, int M2, int M3);
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s);
 
+// Fused rounds of a ragged batch: one launch per stage (pass 1, pass 2, pass 3, the W
+// reduction) runs one k batch of each of several plans that share the working
+// precision, a compiled cubic grid and the pass-3 form.  Workgroup g of a fused launch
+// belongs to the last item whose first workgroup of that stage is <= g and runs that
+// item's batch as workgroup g - wg0 of the plan's own launch, so every result is the
+// plan's own, bit for bit.
+constexpr int kFusedStages = 4;
+struct FusedItem {
+    PairBatch B;
+    const void* psi;          // pass-1 density source (the psi argument of launch_pass1)
+    void* X;                  // the plan's stored pair spectra
+    void* Wpart;              // the plan's pass-3 partial sums
+    void* W;                  // the plan's W~
+    const void* tw;           // the plan's twiddles
+    double* parts;            // the plan's pass-2 partials (unused: no Parseval sums in a build)
+    int wg0[kFusedStages];    // first workgroup of this item in each stage's fused grid
+};
+// a batch can join a fused round: compiled cubic grid, the LDS pass kernels (no
+// register-FFT pass), kernel values from the plan's cache, at most 16 output orbitals
+bool fusable(const PairBatch& B);
+// workgroups of each stage for one batch (elem = bytes per complex)
+void fused_workgroups(const PairBatch& B, int elem, int out[kFusedStages]);
+// one fused launch of `stage` over items[0, nitems) (device memory), `total` workgroups
+// in all; B0 is any item's batch (they share the kernel form)
+template <typename T>
+hipError_t launch_fused(int stage, const PairBatch& B0, const FusedItem* items, int nitems, unsigned total,
+                        hipStream_t s);
+
 template <typename T>
 hipError_t launch_fill_zero(cplx<T>* p, size_t n, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s);

@@ -24,6 +24,7 @@
 // its potential is the conjugate potential.  A batch then covers the blocks
 // (a, b) with b >= a; the diagonal block stores the pairs i <= j only.
 #include <algorithm>
+#include <cstdint>
 #include <type_traits>
 
 #include "fft.hpp"
@@ -112,17 +113,15 @@ struct P1G {
 };
 
 template <typename T, int NN>
-__global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi,
-                                                             cplx<T>* __restrict__ X,
-                                                             const cplx<T>* __restrict__ twg) {
+__device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, const int bid) {
     using C = P1G<NN>;
     constexpr int R0 = C::R0, R1 = C::R1, S = C::S;
     constexpr int PLANE = NN * NN;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* Qb = Pb + NN * S;
-    const int n1 = blockIdx.x % NN;
-    const int row = blockIdx.x / NN;
+    const int n1 = bid % NN;
+    const int row = bid / NN;
     // row -> (block b, summed orbital i, first slot, first partner j0); the diagonal
     // block (if any) comes first and stores the partners j >= i of row i
     const int nocc = B.nocc, nout = B.nout;
@@ -198,6 +197,11 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const 
             for (int r = 0; r < R1; ++r) store_nt<T>(out + r * R0, u[r]);
         }
     }
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
+    pass1g_body<T, NN>(B, psi, X, twg, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,17 +390,15 @@ struct P2S {
 };
 
 template <typename T, int NN>
-__global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T>* __restrict__ X,
-                                                             const cplx<T>* __restrict__ twg,
-                                                             double* __restrict__ parts, int deriv_only) {
+__device__ __forceinline__ void pass2s_body(const PairBatch& B, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, double* __restrict__ parts, int deriv_only, const int bid) {
     using C = P2S<NN>;
     constexpr int R0 = C::R0, R1 = C::R1, S = C::S, NT = C::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* red = reinterpret_cast<double*>(smem_raw);
     cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(red + NT);
     cplx<T>* buf1 = buf0 + NN * S;
-    const int m2i = blockIdx.x % NN;
-    const int grp = blockIdx.x / NN;
+    const int m2i = bid % NN;
+    const int grp = bid / NN;
     const int P = B.group;
     const int nn = B.nocc * B.nout;
     const int gd = B.diag ? (B.ntri + P - 1) / P : 0;
@@ -533,8 +535,13 @@ __global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T
             if (tid < h) red[tid] += red[tid + h];
             __syncthreads();
         }
-        if (tid == 0) parts[blockIdx.x] = red[0];
+        if (tid == 0) parts[bid] = red[0];
     }
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(P2S<NN>::NT) pass2s_kernel(PairBatch B, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, double* __restrict__ parts, int deriv_only) {
+    pass2s_body<T, NN>(B, X, twg, parts, deriv_only, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,6 +658,7 @@ __global__ void __launch_bounds__(kFftThreads) pass3_kernel(PairBatch B, const c
 // so every stored potential is read from device memory once and the partner
 // orbital psi~_{i b} once per (b, i) rather than once per j.
 constexpr int kPass3Threads = 1024;   // fused pass 3: 16 waves, a few rows per thread
+constexpr int kReduceThreads = 256;   // W reduction over the pass-3 splits
 
 constexpr int colblock(int n, int elem) {
     int w = 128 / elem;
@@ -665,9 +673,7 @@ constexpr int pow2_at_least(int n) {
 }
 
 template <typename T, int NN, int JC>
-__global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, const cplx<T>* __restrict__ X,
-                                                             cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
-                                                             const cplx<T>* __restrict__ twg) {
+__device__ __forceinline__ void pass3f_body(const PairBatch& B, const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W, const cplx<T>* __restrict__ twg, const int bid) {
     constexpr int WB = colblock(NN, (int)sizeof(cplx<T>));
     constexpr int NCB = NN / WB;
     constexpr int LN = JC * WB;                      // FFT lines of the tile: (j, column)
@@ -681,9 +687,9 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* tile = tw + 3 * kMaxN;                  // tile[m2][LNP]
-    const int n1 = blockIdx.x % NN;
-    const int cb = (blockIdx.x / NN) % NCB;
-    const int s = blockIdx.x / (NN * NCB);
+    const int n1 = bid % NN;
+    const int cb = (bid / NN) % NCB;
+    const int s = bid / (NN * NCB);
     const int c0 = cb * WB;
     const int nocc = B.nocc, nout = B.nout;
     const int nn = nocc * nout;
@@ -815,6 +821,11 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
     }
 }
 
+template <typename T, int NN, int JC>
+__global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W, const cplx<T>* __restrict__ twg) {
+    pass3f_body<T, NN, JC>(B, X, Wpart, W, twg, (int)blockIdx.x);
+}
+
 // Pass 3 for the compiled cubic sizes with at most 8 output orbitals: the column
 // block transform along m2 as two-stage lines, stage A fed from the prefetched
 // registers and stage B kept in registers, where the a-side sum (and the b-side
@@ -834,9 +845,7 @@ struct P3S {
 };
 
 template <typename T, int NN>
-__global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, const cplx<T>* __restrict__ X,
-                                                                cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W,
-                                                                const cplx<T>* __restrict__ twg) {
+__device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W, const cplx<T>* __restrict__ twg, const int bid) {
     using C = P3S<T, NN>;
     constexpr int R0 = C::R0, R1 = C::R1, WB = C::WB, LN = C::LN, LNP = C::LNP, NT = C::NT;
     constexpr int NCB = NN / WB;
@@ -845,9 +854,9 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     constexpr int BPT = (BP + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int n1 = blockIdx.x % NN;
-    const int cb = (blockIdx.x / NN) % NCB;
-    const int s = blockIdx.x / (NN * NCB);
+    const int n1 = bid % NN;
+    const int cb = (bid / NN) % NCB;
+    const int s = bid / (NN * NCB);
     const int c0 = cb * WB;
     const int nocc = B.nocc, nout = B.nout;
     const int nn = nocc * nout;
@@ -993,15 +1002,28 @@ __global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, c
     }
 }
 
+template <typename T, int NN>
+__global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_kernel(PairBatch B, const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W, const cplx<T>* __restrict__ twg) {
+    pass3s_body<T, NN>(B, X, Wpart, W, twg, (int)blockIdx.x);
+}
+
 template <typename T>
-__global__ void wreduce_kernel(PairBatch B, const cplx<T>* __restrict__ Wpart, cplx<T>* __restrict__ W) {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void wreduce_body(const PairBatch& B, const cplx<T>* __restrict__ Wpart,
+                                             cplx<T>* __restrict__ W, const int bid) {
+    const size_t n = (size_t)bid * kReduceThreads + threadIdx.x;
     const size_t tot = (size_t)B.nout * B.ng;               // partials: [split][nout][ng]
-    if (n >= tot) return;
-    cplx<T>* w = W + B.woff;                                // the output orbitals at k_a
-    cplx<T> acc = w[n];
-    for (int s = 0; s < B.splits; ++s) acc = cadd<T>(acc, Wpart[(size_t)s * tot + n]);
-    w[n] = acc;
+    if (n < tot) {
+        cplx<T>* w = W + B.woff;                            // the output orbitals at k_a
+        cplx<T> acc = w[n];
+        for (int s = 0; s < B.splits; ++s) acc = cadd<T>(acc, Wpart[(size_t)s * tot + n]);
+        w[n] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kReduceThreads) wreduce_kernel(PairBatch B, const cplx<T>* __restrict__ Wpart,
+                                                                 cplx<T>* __restrict__ W) {
+    wreduce_body<T>(B, Wpart, W, (int)blockIdx.x);
 }
 
 template <typename T>
@@ -1183,7 +1205,130 @@ hipError_t launch_pass3(const PairBatch& B, const cplx<T>* X, const cplx<T>* psi
 template <typename T>
 hipError_t launch_wreduce(const PairBatch& B, const cplx<T>* Wpart, cplx<T>* W, hipStream_t s) {
     const size_t tot = (size_t)B.nout * B.ng;
-    hipLaunchKernelGGL(wreduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, Wpart, W);
+    hipLaunchKernelGGL(wreduce_kernel<T>, dim3((unsigned)((tot + kReduceThreads - 1) / kReduceThreads)),
+                       dim3(kReduceThreads), 0, s, B, Wpart, W);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused rounds of a ragged batch
+// ---------------------------------------------------------------------------
+namespace {
+
+// the item of fused workgroup g in `stage`: the last one whose first workgroup is <= g
+__device__ __forceinline__ int fused_item(const FusedItem* __restrict__ items, int nitems, int stage, int g) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].wg0[stage] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Every workgroup of a fused launch runs one workgroup of one item's own launch, with
+// the block size and LDS of the plan's own launcher.
+template <typename T, int NN>
+__global__ void __launch_bounds__(P1G<NN>::NT) pass1g_fused(const FusedItem* __restrict__ items, int nitems,
+                                                            int total) {
+    const int g = blockIdx.x;
+    if (g >= total) return;
+    const FusedItem& it = items[fused_item(items, nitems, 0, g)];
+    pass1g_body<T, NN>(it.B, static_cast<const cplx<T>*>(it.psi), static_cast<cplx<T>*>(it.X),
+                       static_cast<const cplx<T>*>(it.tw), g - it.wg0[0]);
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(P2S<NN>::NT) pass2s_fused(const FusedItem* __restrict__ items, int nitems,
+                                                            int total) {
+    const int g = blockIdx.x;
+    if (g >= total) return;
+    const FusedItem& it = items[fused_item(items, nitems, 1, g)];
+    pass2s_body<T, NN>(it.B, static_cast<cplx<T>*>(it.X), static_cast<const cplx<T>*>(it.tw), it.parts, 0,
+                       g - it.wg0[1]);
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__((P3S<T, NN>::NT)) pass3s_fused(const FusedItem* __restrict__ items, int nitems,
+                                                                int total) {
+    const int g = blockIdx.x;
+    if (g >= total) return;
+    const FusedItem& it = items[fused_item(items, nitems, 2, g)];
+    pass3s_body<T, NN>(it.B, static_cast<const cplx<T>*>(it.X), static_cast<cplx<T>*>(it.Wpart),
+                       static_cast<cplx<T>*>(it.W), static_cast<const cplx<T>*>(it.tw), g - it.wg0[2]);
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(kPass3Threads) pass3f_fused(const FusedItem* __restrict__ items, int nitems,
+                                                              int total) {
+    const int g = blockIdx.x;
+    if (g >= total) return;
+    const FusedItem& it = items[fused_item(items, nitems, 2, g)];
+    pass3f_body<T, NN, 16>(it.B, static_cast<const cplx<T>*>(it.X), static_cast<cplx<T>*>(it.Wpart),
+                           static_cast<cplx<T>*>(it.W), static_cast<const cplx<T>*>(it.tw), g - it.wg0[2]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kReduceThreads) wreduce_fused(const FusedItem* __restrict__ items, int nitems,
+                                                                int total) {
+    const int g = blockIdx.x;
+    if (g >= total) return;
+    const FusedItem& it = items[fused_item(items, nitems, 3, g)];
+    wreduce_body<T>(it.B, static_cast<const cplx<T>*>(it.Wpart), static_cast<cplx<T>*>(it.W), g - it.wg0[3]);
+}
+
+// the pass kernels of one fused stage, with the block size and LDS of the plan's own
+// launchers (launch_pass1g, launch_pass2s, launch_pass3s and the 16-line pass 3)
+template <typename T, int NN>
+void launch_fused_pass(int stage, int nout, const FusedItem* items, int nitems, int total, hipStream_t s) {
+    const unsigned grid = (unsigned)total;
+    if constexpr (NN > 0) {
+        if (stage == 0) {
+            using C = P1G<NN>;
+            hipLaunchKernelGGL((pass1g_fused<T, NN>), dim3(grid), dim3(C::NT), 2 * sizeof(cplx<T>) * NN * C::S, s,
+                               items, nitems, total);
+        } else if (stage == 1) {
+            using C = P2S<NN>;
+            hipLaunchKernelGGL((pass2s_fused<T, NN>), dim3(grid), dim3(C::NT),
+                               sizeof(double) * C::NT + 2 * sizeof(cplx<T>) * NN * C::S, s, items, nitems, total);
+        } else if (nout <= 8) {
+            using C = P3S<T, NN>;
+            hipLaunchKernelGGL((pass3s_fused<T, NN>), dim3(grid), dim3(C::NT), 3 * sizeof(cplx<T>) * NN * C::LNP, s,
+                               items, nitems, total);
+        } else {
+            constexpr int lnp = pow2_at_least(16 * colblock(NN, (int)sizeof(cplx<T>)));
+            hipLaunchKernelGGL((pass3f_fused<T, NN>), dim3(grid), dim3(kPass3Threads),
+                               sizeof(cplx<T>) * (3 * kMaxN + (size_t)NN * lnp), s, items, nitems, total);
+        }
+    }
+}
+
+}  // namespace
+
+bool fusable(const PairBatch& B) {
+    return specialised(B) > 0 && B.regfft == 0 && B.kcache && B.kvals && B.nout <= 16 && !B.parseval;
+}
+
+void fused_workgroups(const PairBatch& B, int elem, int out[kFusedStages]) {
+    const int nn = specialised(B);
+    const int rows = (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * B.nocc;
+    out[0] = nn * rows;                                                  // launch_pass1g
+    out[1] = B.N2 * pair_groups(B);                                      // launch_pass2s
+    out[2] = nn * (nn / colblock(nn, elem)) * B.splits;                  // launch_pass3s / pass3f
+    out[3] = (int)(((size_t)B.nout * B.ng + kReduceThreads - 1) / kReduceThreads);   // launch_wreduce
+}
+
+template <typename T>
+hipError_t launch_fused(int stage, const PairBatch& B0, const FusedItem* items, int nitems, unsigned total,
+                        hipStream_t s) {
+    if (total == 0 || total > (unsigned)INT32_MAX || nitems <= 0 || !fusable(B0) || stage < 0 ||
+        stage >= kFusedStages)
+        return hipErrorInvalidValue;
+    if (stage == 3) {
+        hipLaunchKernelGGL((wreduce_fused<T>), dim3(total), dim3(kReduceThreads), 0, s, items, nitems, (int)total);
+    } else {
+        OCCRIK_DISPATCH(specialised(B0), (launch_fused_pass<T, NN>(stage, B0.nout, items, nitems, (int)total, s)));
+    }
     return hipGetLastError();
 }
 
@@ -1211,7 +1356,8 @@ hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t s) {
                                         const cplx<T>*, hipStream_t);                                           \
     template hipError_t launch_kcache<T>(const PairBatch&, void*, hipStream_t);                              \
     template hipError_t launch_wreduce<T>(const PairBatch&, const cplx<T>*, cplx<T>*, hipStream_t);            \
-    template hipError_t launch_fill_zero<T>(cplx<T>*, size_t, hipStream_t);
+    template hipError_t launch_fill_zero<T>(cplx<T>*, size_t, hipStream_t);                                  \
+    template hipError_t launch_fused<T>(int, const PairBatch&, const FusedItem*, int, unsigned, hipStream_t);
 OCCRIK_INST(float)
 OCCRIK_INST(double)
 #undef OCCRIK_INST

@@ -10,10 +10,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -531,8 +533,24 @@ PairBatch make_batch(const occrik_plan* P, int a, int b0, int nb, bool occ_only 
     return B;
 }
 
+// Stages of a build.  A batch recorded with fused rounds runs the prologue and the
+// epilogue of each plan through build_impl and the pair loop of several plans at once.
+enum : int { kStagePrologue = 1, kStagePairs = 2, kStageEpilogue = 4, kStageAll = 7 };
+
+// the pair-pass launches of one build, in the order the pair loop issues them
+std::vector<PairBatch> plan_launches(const occrik_plan* P) {
+    std::vector<PairBatch> v;
+    const bool reuse = plan_reuses_pairs(P);
+    for (int a = 0; a < P->nk; ++a)
+        for (int b0 = reuse ? a : 0; b0 < P->nk; b0 += P->kbatch)
+            v.push_back(make_batch(P, a, b0, std::min(P->kbatch, P->nk - b0)));
+    return v;
+}
+
 template <typename T>
-occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2* dKmi, double* dEx) {
+occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2* dKmi, double* dEx,
+                         int stages = kStageAll) {
+    if (stages != kStageAll && P->profiling) return fail(OCCRIK_ERR_INVALID_ARG, "profiling needs whole builds");
     hipStream_t s = P->stream;
     const int nk = P->nk, nao = P->nao, nocc = P->nout, ng = P->ng;   // nocc here: columns of C
     cplx<T>* chi = reinterpret_cast<cplx<T>*>(P->chi);
@@ -546,35 +564,38 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
         for (auto& e : pe.e) OCCRIK_HIP(hipEventCreate(&e));
         OCCRIK_HIP(hipEventRecord(pe.e[0], s));
     }
-    OCCRIK_HIP(launch_reset_flags_n(P->flags, 2 + nk, s));
-    OCCRIK_HIP(launch_check_finite(dC, (size_t)nk * nao * nocc, P->flags, s));
-    if (P->direct) {
-        cplx<T>* ws = reinterpret_cast<cplx<T>*>(P->chi_ws);
-        for (int n0 = 0; n0 < ng; n0 += P->cchunk) {
-            const int cnt = std::min(P->cchunk, ng - n0);
-            const occrik_status st = collocate_range<T>(P, n0, cnt, ws, (size_t)cnt, 0);
-            if (st != OCCRIK_OK) return st;
-            OCCRIK_HIP(launch_orbitals<T>(ws, (size_t)cnt, dC, psi, nk, nao, nocc, ng, n0, cnt, P->params.precision, s));
+    if (stages & kStagePrologue) {
+        OCCRIK_HIP(launch_reset_flags_n(P->flags, 2 + nk, s));
+        OCCRIK_HIP(launch_check_finite(dC, (size_t)nk * nao * nocc, P->flags, s));
+        if (P->direct) {
+            cplx<T>* ws = reinterpret_cast<cplx<T>*>(P->chi_ws);
+            for (int n0 = 0; n0 < ng; n0 += P->cchunk) {
+                const int cnt = std::min(P->cchunk, ng - n0);
+                const occrik_status st = collocate_range<T>(P, n0, cnt, ws, (size_t)cnt, 0);
+                if (st != OCCRIK_OK) return st;
+                OCCRIK_HIP(launch_orbitals<T>(ws, (size_t)cnt, dC, psi, nk, nao, nocc, ng, n0, cnt,
+                                              P->params.precision, s));
+            }
+        } else {
+            OCCRIK_HIP(launch_orbitals<T>(chi, (size_t)ng, dC, psi, nk, nao, nocc, ng, 0, ng, P->params.precision, s));
         }
-    } else {
-        OCCRIK_HIP(launch_orbitals<T>(chi, (size_t)ng, dC, psi, nk, nao, nocc, ng, 0, ng, P->params.precision, s));
-    }
-    if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
-    OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
-    // kernel values of every k-point difference, once per omega; under stream capture the
-    // fill is recorded into the graph (and replayed with it) and the plan stays unfilled
-    if (P->kcache && (!P->kcache_valid || P->kcache_omega != P->params.omega)) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        OCCRIK_HIP(hipStreamIsCapturing(s, &cs));
-        OCCRIK_HIP(launch_kcache<T>(make_batch(P, 0, 0, 1), P->kcache, s));
-        if (cs == hipStreamCaptureStatusNone) {
-            P->kcache_valid = true;
-            P->kcache_omega = P->params.omega;
+        if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[1], s));
+        OCCRIK_HIP(launch_fill_zero<T>(W, (size_t)nk * nocc * ng, s));
+        // kernel values of every k-point difference, once per omega; under stream capture the
+        // fill is recorded into the graph (and replayed with it) and the plan stays unfilled
+        if (P->kcache && (!P->kcache_valid || P->kcache_omega != P->params.omega)) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            OCCRIK_HIP(hipStreamIsCapturing(s, &cs));
+            OCCRIK_HIP(launch_kcache<T>(make_batch(P, 0, 0, 1), P->kcache, s));
+            if (cs == hipStreamCaptureStatusNone) {
+                P->kcache_valid = true;
+                P->kcache_omega = P->params.omega;
+            }
         }
     }
     int64_t launches = 1;
     const bool reuse = plan_reuses_pairs(P);
-    for (int a = 0; a < nk; ++a) {
+    for (int a = 0; a < nk && (stages & kStagePairs); ++a) {
         for (int b0 = reuse ? a : 0; b0 < nk; b0 += P->kbatch) {
             const int nb = std::min(P->kbatch, nk - b0);
             PairBatch B = make_batch(P, a, b0, nb);
@@ -600,6 +621,7 @@ occrik_status build_impl(occrik_plan* P, const double2* dC, double2* dK, double2
             launches += 4;
         }
     }
+    if (!(stages & kStageEpilogue)) return OCCRIK_OK;
     if (P->profiling) OCCRIK_HIP(hipEventRecord(pe.e[2], s));
     {
         const int chunk = contract_chunk(ng, P->nchunks);
@@ -940,9 +962,13 @@ occrik_status occrik_plan_create(const occrik_cell* cell, const occrik_basis* ba
     P->splits = splits_for(P, P->kbatch);
     P->group = nout;
     // every chunk holds grid points: the integral-direct contraction launches only the
-    // chunks a collocation chunk covers, so an empty trailing chunk would never be written
-    P->nchunks = contract_chunk_count(
-        ng, params->contract_chunks > 0 ? params->contract_chunks : std::max(1, std::min(64, ng / 4096)));
+    // chunks a collocation chunk covers, so an empty trailing chunk would never be written.
+    // By default one chunk per 4096 points, and more (up to 64) where that leaves the
+    // contraction's launch (chunks x 64-AO blocks x k-points) below 2048 workgroups: a
+    // small cell's few long-running workgroups would leave most of the chip idle.
+    const int wg_per_chunk = nk * ((nao + 63) / 64);
+    const int nchunks_default = std::max(1, std::min(64, std::max(ng / 4096, (2048 + wg_per_chunk - 1) / wg_per_chunk)));
+    P->nchunks = contract_chunk_count(ng, params->contract_chunks > 0 ? params->contract_chunks : nchunks_default);
     const size_t max_groups = (size_t)P->kbatch * ((nocc * nout + P->group - 1) / P->group) +
                               (nocc * (nocc + 1) / 2 + P->group - 1) / P->group;
 
@@ -1360,6 +1386,7 @@ occrik_status occrik_grad(occrik_plan* P, double gEx, void* dgradC, double* dgra
 // device (fork and join on the plans' stream), either enqueued directly or
 // recorded once as a HIP graph and replayed with one launch
 // ---------------------------------------------------------------------------
+extern "C++" {
 namespace {
 
 constexpr int kBatchStreams = 4;
@@ -1454,16 +1481,203 @@ occrik_status enqueue_batch(int32_t n, occrik_plan* const* plans, const void* co
     return st;
 }
 
+// Fused rounds of a recorded batch.  Plans that share the working precision, a compiled
+// cubic grid and the pass-3 form (up to 8 or 9-16 output orbitals) form a group; round r
+// of a group runs the r-th pair-pass launch of each of its plans as one launch per stage
+// (pass 1, pass 2, pass 3, the W reduction).  Each plan's launches keep their order, so
+// every result is the plan's own single build, bit for bit.
+struct FusedGroup {
+    bool fp64 = false;
+    PairBatch B0{};                          // the first batch of the group (kernel forms)
+    std::vector<int> plans;                  // indices into the batch
+    std::vector<int> round_off, round_n;     // items of each round in the device table
+    std::vector<std::array<unsigned, kFusedStages>> round_total;
+};
+
+struct FusedSchedule {
+    std::vector<FusedGroup> groups;
+    std::vector<FusedItem> items;            // every round of every group, in launch order
+    std::vector<char> fused;                 // per plan: 1 if its pair passes run in a group
+};
+
+FusedSchedule plan_fused(int32_t n, occrik_plan* const* plans) {
+    FusedSchedule f;
+    f.fused.assign(n, 0);
+    std::vector<std::vector<PairBatch>> launches(n);
+    std::map<std::array<int, 3>, std::vector<int>> by_key;
+    for (int i = 0; i < n; ++i) {
+        launches[i] = plan_launches(plans[i]);
+        bool ok = !launches[i].empty();
+        for (const PairBatch& B : launches[i]) ok = ok && fusable(B);
+        if (ok) by_key[{plans[i]->fp64 ? 1 : 0, launches[i][0].N1, launches[i][0].nout <= 8 ? 8 : 16}].push_back(i);
+    }
+    for (auto& kv : by_key) {
+        if (kv.second.size() < 2) continue;                // a single plan gains nothing
+        FusedGroup g;
+        g.fp64 = kv.first[0] != 0;
+        g.plans = kv.second;
+        g.B0 = launches[g.plans[0]][0];
+        size_t rounds = 0;
+        for (int i : g.plans) rounds = std::max(rounds, launches[i].size());
+        for (size_t r = 0; r < rounds; ++r) {
+            std::array<size_t, kFusedStages> tot{};
+            const int off = (int)f.items.size();
+            for (int i : g.plans) {
+                if (r >= launches[i].size()) continue;
+                const occrik_plan* P = plans[i];
+                FusedItem it{};
+                it.B = launches[i][r];
+                it.psi = P->psi;
+                it.X = P->X;
+                it.Wpart = P->Wpart;
+                it.W = P->W;
+                it.tw = P->tw;
+                it.parts = P->parts;
+                int wg[kFusedStages];
+                fused_workgroups(it.B, (int)P->elem, wg);
+                for (int st = 0; st < kFusedStages; ++st) {
+                    it.wg0[st] = (int)tot[st];
+                    tot[st] += (size_t)wg[st];
+                }
+                f.items.push_back(it);
+            }
+            std::array<unsigned, kFusedStages> t{};
+            for (int st = 0; st < kFusedStages; ++st) t[st] = tot[st] <= (size_t)INT_MAX ? (unsigned)tot[st] : 0u;
+            g.round_off.push_back(off);
+            g.round_n.push_back((int)f.items.size() - off);
+            g.round_total.push_back(t);
+        }
+        for (int i : g.plans) f.fused[i] = 1;
+        f.groups.push_back(std::move(g));
+    }
+    return f;
+}
+
+template <typename T>
+occrik_status build_stages(occrik_plan* P, const void* dC, void* dK, void* dKmi, double* dEx, int stages) {
+    return build_impl<T>(P, (const double2*)dC, (double2*)dK, (double2*)dKmi, dEx, stages);
+}
+
+occrik_status build_plan_stages(occrik_plan* P, const void* dC, void* dK, void* dKmi, double* dEx, int stages) {
+    return P->fp64 ? build_stages<double>(P, dC, dK, dKmi, dEx, stages)
+                   : build_stages<float>(P, dC, dK, dKmi, dEx, stages);
+}
+
+// The fused form of enqueue_batch (inside the recording of a batch graph): the
+// prologues (orbitals, W zero, kernel values) of the grouped plans spread over the
+// worker streams; then each group's rounds on one worker, the groups assigned largest
+// first to the least-loaded worker, beside the other plans' whole builds; then the
+// grouped plans' epilogues (contraction, assembly, E_x) spread over the workers.  The
+// plans' stream joins the workers between the phases.  ev holds 4 + 3 kBatchStreams
+// events.
+occrik_status enqueue_fused(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                            void* const* dKmi, double* const* dEx, const FusedSchedule& f, const FusedItem* d_items,
+                            const hipEvent_t* ev) {
+    hipStream_t s0 = plans[0]->stream;
+    BatchStreams* bs = nullptr;
+    OCCRIK_HIP(batch_streams(plans[0]->device, &bs));
+    const hipEvent_t* fork = ev;                          // [3] s0 -> workers before each phase
+    const hipEvent_t* join = ev + 4;                      // [3][kBatchStreams] workers -> s0 after each phase
+    auto arg = [](auto* const* a, int i) { return a ? a[i] : nullptr; };
+    occrik_status st = OCCRIK_OK;
+    auto phase_begin = [&](int k) -> occrik_status {
+        OCCRIK_HIP(hipEventRecord(fork[k], s0));
+        for (int w = 0; w < kBatchStreams; ++w) OCCRIK_HIP(hipStreamWaitEvent(bs->s[w], fork[k], 0));
+        return OCCRIK_OK;
+    };
+    auto phase_end = [&](int k) -> occrik_status {
+        for (int w = 0; w < kBatchStreams; ++w) {
+            OCCRIK_HIP(hipEventRecord(join[k * kBatchStreams + w], bs->s[w]));
+            OCCRIK_HIP(hipStreamWaitEvent(s0, join[k * kBatchStreams + w], 0));
+        }
+        return OCCRIK_OK;
+    };
+    auto on_worker = [&](int i, int w, int stages) {
+        occrik_plan* P = plans[i];
+        P->stream = bs->s[w];
+        P->last_err_k = -1;
+        const occrik_status r = build_plan_stages(P, dC[i], arg(dK, i), arg(dKmi, i), arg(dEx, i), stages);
+        P->stream = s0;
+        return r;
+    };
+    // phase 1: prologues of the grouped plans
+    if ((st = phase_begin(0)) != OCCRIK_OK) return st;
+    int w = 0;
+    for (int i = 0; i < n && st == OCCRIK_OK; ++i)
+        if (f.fused[i]) {
+            st = on_worker(i, w, kStagePrologue);
+            w = (w + 1) % kBatchStreams;
+        }
+    occrik_status e = phase_end(0);
+    if (st == OCCRIK_OK) st = e;
+    // phase 2: each group's rounds on one worker, the other plans whole, largest first
+    // to the least-loaded worker
+    if (st == OCCRIK_OK) st = phase_begin(1);
+    struct Job {
+        double cost;
+        int group, plan;
+    };
+    std::vector<Job> jobs;
+    for (size_t g = 0; g < f.groups.size(); ++g) {
+        double c = 0.0;
+        for (int i : f.groups[g].plans) c += build_cost(plans[i]);
+        jobs.push_back({c, (int)g, -1});
+    }
+    for (int i = 0; i < n; ++i)
+        if (!f.fused[i]) jobs.push_back({build_cost(plans[i]), -1, i});
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
+    double load[kBatchStreams] = {};
+    for (const Job& j : jobs) {
+        if (st != OCCRIK_OK) break;
+        const int v = int(std::min_element(load, load + kBatchStreams) - load);
+        load[v] += j.cost;
+        if (j.plan >= 0) {
+            st = on_worker(j.plan, v, kStageAll);
+            continue;
+        }
+        const FusedGroup& g = f.groups[j.group];
+        for (size_t r = 0; r < g.round_off.size() && st == OCCRIK_OK; ++r) {
+            for (int stage = 0; stage < kFusedStages && st == OCCRIK_OK; ++stage) {
+                const unsigned total = g.round_total[r][stage];
+                const FusedItem* items = d_items + g.round_off[r];
+                const hipError_t he = g.fp64
+                                          ? launch_fused<double>(stage, g.B0, items, g.round_n[r], total, bs->s[v])
+                                          : launch_fused<float>(stage, g.B0, items, g.round_n[r], total, bs->s[v]);
+                if (he != hipSuccess) st = hip_fail(he, "launch_fused");
+            }
+        }
+    }
+    // join even after a failed enqueue, so that the plans' stream never runs ahead of the workers
+    e = phase_end(1);
+    if (st == OCCRIK_OK) st = e;
+    // phase 3: epilogues of the grouped plans
+    if (st == OCCRIK_OK) st = phase_begin(2);
+    w = 0;
+    for (int i = 0; i < n && st == OCCRIK_OK; ++i)
+        if (f.fused[i]) {
+            st = on_worker(i, w, kStageEpilogue);
+            w = (w + 1) % kBatchStreams;
+        }
+    e = phase_end(2);
+    return st != OCCRIK_OK ? st : e;
+}
+
 }  // namespace
+}  // extern "C++"
 
 struct occrik_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    FusedItem* d_items = nullptr;            // the fused rounds' item table (read by the graph)
+    std::vector<hipEvent_t> events;          // fork and join events of the fused schedule
+    int fused_plans = 0;
     ~occrik_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (d_items) (void)hipFree(d_items);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
 };
 
@@ -1475,8 +1689,12 @@ occrik_status occrik_build_batch(int32_t n, occrik_plan* const* plans, const voi
     return enqueue_batch(n, plans, dC, dK, dKmi, dEx);
 }
 
-occrik_status occrik_batch_create(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
-                                  void* const* dKmi, double* const* dEx, occrik_batch** out) {
+}  // extern "C"
+
+namespace {
+
+occrik_status batch_create(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                           void* const* dKmi, double* const* dEx, bool fuse, occrik_batch** out) {
     if (!out) return fail(OCCRIK_ERR_INVALID_ARG, "null out");
     *out = nullptr;
     occrik_status st = validate_batch(n, plans, dC);
@@ -1491,12 +1709,32 @@ occrik_status occrik_batch_create(int32_t n, occrik_plan* const* plans, const vo
     auto* b = new occrik_batch();
     b->device = plans[0]->device;
     b->stream = plans[0]->stream;
-    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+    // fused rounds for the plans that share a kernel form: the item table is uploaded and
+    // the events created before the recording starts
+    const FusedSchedule f = fuse ? plan_fused(n, plans) : FusedSchedule{};
+    hipError_t e = hipSuccess;
+    if (!f.groups.empty()) {
+        const size_t bytes = sizeof(FusedItem) * f.items.size();
+        e = hipMalloc((void**)&b->d_items, bytes);
+        if (e == hipSuccess) e = hipMemcpy(b->d_items, f.items.data(), bytes, hipMemcpyHostToDevice);
+        for (int k = 0; k < 4 + 3 * kBatchStreams && e == hipSuccess; ++k) {
+            hipEvent_t ev = nullptr;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) b->events.push_back(ev);
+        }
+        for (const FusedGroup& g : f.groups) b->fused_plans += (int)g.plans.size();
+        if (e != hipSuccess) {
+            delete b;
+            return hip_fail(e, "fused batch set-up");
+        }
+    }
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
         delete b;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    st = enqueue_batch(n, plans, dC, dK, dKmi, dEx);
+    st = f.groups.empty() ? enqueue_batch(n, plans, dC, dK, dKmi, dEx)
+                          : enqueue_fused(n, plans, dC, dK, dKmi, dEx, f, b->d_items, b->events.data());
     e = hipStreamEndCapture(b->stream, &b->graph);
     if (st != OCCRIK_OK || e != hipSuccess) {
         delete b;
@@ -1511,10 +1749,30 @@ occrik_status occrik_batch_create(int32_t n, occrik_plan* const* plans, const vo
     return OCCRIK_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+occrik_status occrik_batch_create(int32_t n, occrik_plan* const* plans, const void* const* dC, void* const* dK,
+                                  void* const* dKmi, double* const* dEx, occrik_batch** out) {
+    return batch_create(n, plans, dC, dK, dKmi, dEx, false, out);
+}
+
+occrik_status occrik_batch_create_fused(int32_t n, occrik_plan* const* plans, const void* const* dC,
+                                        void* const* dK, void* const* dKmi, double* const* dEx, occrik_batch** out) {
+    return batch_create(n, plans, dC, dK, dKmi, dEx, true, out);
+}
+
 occrik_status occrik_batch_launch(occrik_batch* b) {
     if (!b) return fail(OCCRIK_ERR_INVALID_ARG, "null batch");
     DeviceGuard guard(b->device);
     OCCRIK_HIP(hipGraphLaunch(b->exec, b->stream));
+    return OCCRIK_OK;
+}
+
+occrik_status occrik_batch_fused(const occrik_batch* b, int32_t* nplans) {
+    if (!b || !nplans) return fail(OCCRIK_ERR_INVALID_ARG, "null batch or out");
+    *nplans = b->fused_plans;
     return OCCRIK_OK;
 }
 

@@ -279,9 +279,11 @@ class BatchGraph:
     """occrik_batch_create / occrik_batch_launch / occrik_batch_destroy: a ragged batch
     recorded once as a HIP graph and replayed with one launch.  The plans must share a
     non-default stream (the current one when recorded); the plans and tensors passed
-    here must stay alive while the object is used."""
+    here must stay alive while the object is used.  ``fused=True`` records it with
+    occrik_batch_create_fused (fused pair-pass rounds for plans that share a kernel
+    form); ``self.fused`` is the number of plans that run in such rounds."""
 
-    def __init__(self, plans, Cs, Ks=None, Kmis=None, Exs=None):
+    def __init__(self, plans, Cs, Ks=None, Kmis=None, Exs=None, fused=False):
         lib = _lib.load()
         n = len(plans)
         for p in plans:
@@ -293,9 +295,12 @@ class BatchGraph:
         self._h = ctypes.c_void_p()
         for p in plans:
             p.generation += 1
-        check(lib.occrik_batch_create(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none),
-                                      ctypes.byref(self._h)))
+        create = lib.occrik_batch_create_fused if fused else lib.occrik_batch_create
+        check(create(n, hp, arr(Cs), arr(Ks or none), arr(Kmis or none), arr(Exs or none), ctypes.byref(self._h)))
         self._lib = lib
+        nf = ctypes.c_int32()
+        check(lib.occrik_batch_fused(self._h, ctypes.byref(nf)))
+        self.fused = nf.value          # plans whose pair passes run in fused rounds
 
     def launch(self):
         for p in self._keep[0]:

@@ -134,8 +134,9 @@ def batch_problems(cells: int, small: bool):
 
 def time_batch(probs, precision: int, reps: int = 3, autotune: bool = False) -> dict:
     """Plans for every cell (Bloch AOs stored), then ms per batch: one build after
-    another on one stream, the concurrent batch, and the recorded graph's replay (HIP
-    events, each after one untimed pass).  Returns a dict of the timings."""
+    another on one stream, the concurrent batch, the recorded graph's replay and the
+    replay of the graph recorded with fused pair-pass rounds (HIP events, each after one
+    untimed pass).  Returns a dict of the timings."""
     side = torch.cuda.Stream()
     out = dict(cells=len(probs), precision=int(precision), autotune=bool(autotune))
     with torch.cuda.stream(side):
@@ -179,6 +180,12 @@ def time_batch(probs, precision: int, reps: int = 3, autotune: bool = False) -> 
         for plan in plans:
             plan.status()
         graph.close()
+        fused = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es, fused=True)
+        out["ms_graph_fused"] = round(timed(fused.launch), 3)
+        out["fused_plans"] = fused.fused
+        for plan in plans:
+            plan.status()
+        fused.close()
         out["builds_per_s_graph"] = round(len(probs) / (out["ms_graph"] * 1e-3), 3)
         out["Ex_sum"] = float(sum(float(E[0]) for E in Es))
         for plan in plans:

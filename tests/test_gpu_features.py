@@ -256,6 +256,65 @@ def test_batch_graph_replays_match_eager_builds():
         graph.close()
 
 
+def test_fused_batch_rounds_match_single_builds():
+    """With occrik_batch_create_fused, plans that share a kernel form run their pair
+    passes in fused rounds, one launch per pass for several cells: complex64 plans on 24^3 (FP32 and FP32-split, one with
+    conduction-band columns) with the 8-line pass 3, complex64 plans with 10 occupied
+    orbitals on 24^3 (16-line pass 3) and FP64 plans on 30^3, on ragged k-meshes; one
+    plan on a run-time grid builds whole beside them.  Every replay equals the single
+    eager builds bitwise, and the FP64 members match the oracle."""
+    cases = [
+        (dict(kmesh=(2, 1, 2), grid=(24, 24, 24), nocc=3, seed=61), dict(precision=pkg.PREC_FP32_SPLIT)),
+        (dict(kmesh=(1, 2, 1), grid=(24, 24, 24), nocc=4, counts=(2, 2, 1), seed=62), dict(precision=pkg.PREC_FP32)),
+        (dict(kmesh=(2, 2, 1), grid=(24, 24, 24), nocc=5, counts=(2, 2, 1), seed=63),
+         dict(precision=pkg.PREC_FP32_SPLIT, nocc=3, nvir=2)),
+        (dict(kmesh=(1, 1, 2), grid=(24, 24, 24), nocc=10, counts=(2, 2, 1), seed=64),
+         dict(precision=pkg.PREC_FP32_SPLIT)),
+        (dict(kmesh=(2, 1, 1), grid=(24, 24, 24), nocc=10, counts=(2, 2, 1), seed=65), dict(precision=pkg.PREC_FP32)),
+        (dict(kmesh=(1, 2, 2), grid=(30, 30, 30), nocc=3, seed=66), dict(precision=pkg.PREC_FP64)),
+        (dict(kmesh=(2, 1, 1), grid=(30, 30, 30), nocc=4, counts=(2, 1, 1), seed=67), dict(precision=pkg.PREC_FP64)),
+        (dict(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=68), dict(precision=pkg.PREC_FP32_SPLIT)),
+    ]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        probs, plans, Cs, Ks, Kmis, Es, ref = [], [], [], [], [], [], []
+        for pk, sk in cases:
+            prob = W.small_problem(**pk)
+            C = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+            plan = Plan(PlanSpec.from_problem(prob, **sk))
+            r = plan.build(C)
+            ref.append({k: v.clone() for k, v in r.items()})
+            probs.append(prob)
+            plans.append(plan)
+            Cs.append(C)
+            Ks.append(torch.empty_like(r["K"]))
+            Kmis.append(torch.empty_like(r["Kmi"]))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es, fused=True)
+        assert graph.fused == 7
+        plain = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es)
+        assert plain.fused == 0
+        plain.close()
+        for rep in range(2):
+            for t in Ks + Kmis + Es:
+                t.fill_(float("nan"))
+            graph.launch()
+            side.synchronize()
+            for i in range(len(cases)):
+                plans[i].status()
+                assert torch.equal(Ks[i], ref[i]["K"]), (rep, i)
+                assert torch.equal(Kmis[i], ref[i]["Kmi"]), (rep, i)
+                assert torch.equal(Es[i], ref[i]["Ex"]), (rep, i)
+        graph.close()
+    for i in (5, 6):
+        prob = probs[i]
+        chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+        o = occrik.build(prob, Cs[i].cpu().numpy(), chi=chi, nyquist="symmetric")
+        K = ref[i]["K"].cpu().numpy()
+        assert np.max(np.abs(K - o["K"])) < 1e-10 * np.max(np.abs(o["K"])), i
+        assert abs(float(ref[i]["Ex"][0]) - o["Ex"]) < 1e-10 * abs(o["Ex"]), i
+
+
 def test_ragged_batch_equals_single_builds_bitwise():
     probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
              W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=2, counts=(1, 1, 1), seed=2),
