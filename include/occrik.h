@@ -166,9 +166,11 @@ typedef struct {
                                      columns (K~ C_p equals the conventional K C_p for every
                                      column), E_x is the occupied trace.  0 = ground state. */
     int32_t contract_chunks;      /* grid chunks of the contraction's FP64 partial sums, 1..64;
-                                     0 = chosen by the plan (N_g / 4096, clamped).  Chunks hold
-                                     whole multiples of 16 points, so the plan keeps only the
-                                     chunks that hold grid points (occrik_plan_info reports it) */
+                                     0 = chosen by the plan (N_g / 4096, or more where the
+                                     contraction's launch would hold fewer than 2048
+                                     workgroups; at most 64).  Chunks hold whole multiples of
+                                     16 points, so the plan keeps only the chunks that hold
+                                     grid points (occrik_plan_info reports it) */
 } occrik_params;
 
 typedef struct occrik_plan occrik_plan;
