@@ -95,15 +95,20 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
     }
 }
 
-// Pass 1 for the compiled cubic sizes, one workgroup per x-plane and row of stored
-// pairs (one summed orbital i of block b with all its partners j): psi~_{i b} on
-// the plane is held in registers for the whole row and the next partner's plane is
-// loaded while the current pair is transformed.  The plane transform runs as
-// two-stage lines: stage A of axis n2 on the pair density in registers (lanes
-// along n3), stage B in place, axis n3 from one LDS buffer into a second, and its
-// stage B stored straight to memory.  Stage B items are numbered element-fastest,
-// so eight consecutive lanes store 64 contiguous bytes of a row.  3 barriers and
-// 6 LDS accesses per point per pair.
+// Pass 1 for the compiled cubic sizes, one workgroup per x-plane and group of rows
+// of stored pairs (a row: one summed orbital i of block b with all its partners j;
+// a group: up to four (complex64) or two (complex128) consecutive i of one block on
+// large launches, one on small ones, or one row of the diagonal block): the summed
+// orbitals psi~_{i b} of the group on the plane are held in
+// registers for all their partners, each partner's plane is loaded once for the
+// group's densities, and the next partner's plane is loaded while the current pairs
+// are transformed.  A workgroup waits for device memory at its start, for the held
+// orbitals; with several rows per workgroup that wait is shared by more pairs.  The
+// plane transform runs as two-stage lines: stage A of axis n2 on the pair density in
+// registers (lanes along n3), stage B in place, axis n3 from one LDS buffer into a
+// second, and its stage B stored straight to memory.  Stage B items are numbered
+// element-fastest, so eight consecutive lanes store 64 contiguous bytes of a row.
+// 3 barriers and 6 LDS accesses per point per pair.
 template <int NN>
 struct P1G {
     static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
@@ -112,7 +117,21 @@ struct P1G {
     static constexpr int S = NN + 1;
 };
 
-template <typename T, int NN>
+// pass-1 workgroups per x-plane of a batch: the diagonal block's rows one by one, the
+// other blocks' rows in groups of `rows`
+inline int pass1_groups(const PairBatch& B, int rows) {
+    return (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * ((B.nocc + rows - 1) / rows);
+}
+
+// rows of a block that one pass-1 workgroup holds (elem = bytes per complex): four in
+// complex64 (126 VGPRs at 48^3, two workgroups per CU), two in complex128, where the
+// launch keeps at least 4096 single-row workgroups; one row otherwise, so that a small
+// cell's launch still spreads over the chip
+inline int pass1_rows(const PairBatch& B, int nn, int elem) {
+    return (size_t)nn * pass1_groups(B, 1) >= 4096 ? (elem == 8 ? 4 : 2) : 1;
+}
+
+template <typename T, int NN, int ROWS>
 __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, const int bid) {
     using C = P1G<NN>;
     constexpr int R0 = C::R0, R1 = C::R1, S = C::S;
@@ -121,20 +140,24 @@ __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* _
     cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* Qb = Pb + NN * S;
     const int n1 = bid % NN;
-    const int row = bid / NN;
-    // row -> (block b, summed orbital i, first slot, first partner j0); the diagonal
-    // block (if any) comes first and stores the partners j >= i of row i
+    const int grp = bid / NN;
+    // group -> (block b, first summed orbital i, its rows, first slot, first partner
+    // j0); the diagonal block (if any) comes first, one row per group, and stores the
+    // partners j >= i of row i; row i + h of a group stores at slot0 + h nout + j
     const int nocc = B.nocc, nout = B.nout;
-    int b, i, slot0, j0;
-    if (B.diag && row < nocc) {
+    int b, i, slot0, j0, nrows;
+    if (B.diag && grp < nocc) {
         b = B.a;
-        i = row;
+        i = grp;
         j0 = i;
         slot0 = tri_index(i, i, nocc);
+        nrows = 1;
     } else {
-        const int r = row - (B.diag ? nocc : 0);
-        const int blk = r / nocc;
-        i = r - blk * nocc;
+        const int r = grp - (B.diag ? nocc : 0);
+        const int per_blk = (nocc + ROWS - 1) / ROWS;
+        const int blk = r / per_blk;
+        i = ROWS * (r - blk * per_blk);
+        nrows = ROWS == 1 ? 1 : (nocc - i < ROWS ? nocc - i : ROWS);
         b = B.b0 + (B.diag ? 1 : 0) + blk;
         j0 = 0;
         slot0 = (B.diag ? B.ntri : 0) + blk * nocc * nout + i * nout;
@@ -149,28 +172,36 @@ __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* _
 #pragma unroll
         for (int r = 0; r < R1 - 1; ++r) w[r] = mk<T>(T(0), T(0));
     }
-    // this thread's stage A points (n2 = sj + r R1, n3 = ln) of psi~_{i b}, held
+    // this thread's stage A points (n2 = sj + r R1, n3 = ln) of psi~_{i + h, b}, held
     const size_t poff = (size_t)n1 * PLANE + ln;
     const cplx<T>* pi = psi + ((size_t)b * B.kstride + i) * B.ng + poff;
-    cplx<T> ui[R0], xn[R0];
+    cplx<T> uh[ROWS][R0], xn[R0];
 #pragma unroll
-    for (int r = 0; r < R0; ++r) ui[r] = ha ? load_nt<T>(pi + (size_t)(sj + r * R1) * NN) : mk<T>(T(0), T(0));
+    for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+        for (int r = 0; r < R0; ++r)
+            uh[h][r] = (ha && h < nrows) ? load_nt<T>(pi + (size_t)h * B.ng + (size_t)(sj + r * R1) * NN)
+                                         : mk<T>(T(0), T(0));
     auto load_partner = [&](int j) {
         const cplx<T>* pj = static_cast<const cplx<T>*>(B.outp) + (size_t)j * B.ng + poff;
 #pragma unroll
         for (int r = 0; r < R0; ++r) xn[r] = ha ? pj[(size_t)(sj + r * R1) * NN] : mk<T>(T(0), T(0));
     };
     load_partner(j0);
-    for (int j = j0; j < nout; ++j) {
-        const int slot = slot0 + (j - j0);
+    for (int j = j0; j < nout; ++j)
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+        if (h >= nrows) break;
+        const int slot = slot0 + h * nout + (j - j0);
         // axis n2 (lines n3 = ln, elements n2 at stride S): stage A on the pair density
         if (ha) {
             cplx<T> a[R0];
 #pragma unroll
-            for (int r = 0; r < R0; ++r) a[r] = cjmul<T>(ui[r], xn[r]);
+            for (int r = 0; r < R0; ++r) a[r] = cjmul<T>(uh[h][r], xn[r]);
             stage_a_store<T, NN, -1>(a, Pb + ln, sj, S);
         }
-        if (j + 1 < nout) load_partner(j + 1);
+        // the next partner, once the group's last density of this one is formed
+        if (h == nrows - 1 && j + 1 < nout) load_partner(j + 1);
         __syncthreads();
         if (hb) {
             cplx<T> u[R1];
@@ -199,9 +230,9 @@ __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* _
     }
 }
 
-template <typename T, int NN>
+template <typename T, int NN, int ROWS>
 __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
-    pass1g_body<T, NN>(B, psi, X, twg, (int)blockIdx.x);
+    pass1g_body<T, NN, ROWS>(B, psi, X, twg, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1065,12 +1096,17 @@ inline int specialised(const PairBatch& B) {
     }
 
 template <typename T, int NN>
-void launch_pass1g(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, unsigned grid,
-                   hipStream_t s) {
+void launch_pass1g(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s) {
     if constexpr (NN > 0) {
         using C = P1G<NN>;
+        constexpr int GROUP = sizeof(T) == 4 ? 4 : 2;
         const size_t lds = 2 * sizeof(cplx<T>) * NN * C::S;
-        hipLaunchKernelGGL((pass1g_kernel<T, NN>), dim3(grid), dim3(C::NT), lds, s, B, psi, X, tw);
+        const int rows = pass1_rows(B, NN, (int)sizeof(cplx<T>));
+        const dim3 grid((unsigned)((size_t)NN * pass1_groups(B, rows)));
+        if (rows == GROUP)
+            hipLaunchKernelGGL((pass1g_kernel<T, NN, GROUP>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
+        else
+            hipLaunchKernelGGL((pass1g_kernel<T, NN, 1>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
     }
 }
 
@@ -1120,8 +1156,7 @@ hipError_t launch_pass1(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, cons
     if constexpr (std::is_same_v<T, float>)
         if (B.regfft & REGFFT_PASS1) return launch_pass1_reg(B, psi, X, s);
     if (const int nnv = specialised(B)) {
-        const int rows = (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * B.nocc;
-        OCCRIK_DISPATCH(nnv, (launch_pass1g<T, NN>(B, psi, X, tw, (unsigned)((size_t)NN * rows), s)));
+        OCCRIK_DISPATCH(nnv, (launch_pass1g<T, NN>(B, psi, X, tw, s)));
         return hipGetLastError();
     }
     const unsigned grid = (unsigned)((size_t)B.N1 * B.nslots);
@@ -1234,8 +1269,8 @@ __global__ void __launch_bounds__(P1G<NN>::NT) pass1g_fused(const FusedItem* __r
     const int g = blockIdx.x;
     if (g >= total) return;
     const FusedItem& it = items[fused_item(items, nitems, 0, g)];
-    pass1g_body<T, NN>(it.B, static_cast<const cplx<T>*>(it.psi), static_cast<cplx<T>*>(it.X),
-                       static_cast<const cplx<T>*>(it.tw), g - it.wg0[0]);
+    pass1g_body<T, NN, 1>(it.B, static_cast<const cplx<T>*>(it.psi), static_cast<cplx<T>*>(it.X),
+                          static_cast<const cplx<T>*>(it.tw), g - it.wg0[0]);
 }
 
 template <typename T, int NN>
@@ -1311,8 +1346,7 @@ bool fusable(const PairBatch& B) {
 
 void fused_workgroups(const PairBatch& B, int elem, int out[kFusedStages]) {
     const int nn = specialised(B);
-    const int rows = (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * B.nocc;
-    out[0] = nn * rows;                                                  // launch_pass1g
+    out[0] = nn * pass1_groups(B, 1);                                    // pass1g_fused: one row per group
     out[1] = B.N2 * pair_groups(B);                                      // launch_pass2s
     out[2] = nn * (nn / colblock(nn, elem)) * B.splits;                  // launch_pass3s / pass3f
     out[3] = (int)(((size_t)B.nout * B.ng + kReduceThreads - 1) / kReduceThreads);   // launch_wreduce
