@@ -97,8 +97,8 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
 
 // Pass 1 for the compiled cubic sizes, one workgroup per x-plane and group of rows
 // of stored pairs (a row: one summed orbital i of block b with all its partners j;
-// a group: up to four (complex64) or two (complex128) consecutive i of one block on
-// large launches, one on small ones, or one row of the diagonal block): the summed
+// a group: up to four consecutive i of one block on large launches, one on small
+// ones, or one row of the diagonal block): the summed
 // orbitals psi~_{i b} of the group on the plane are held in
 // registers for all their partners, each partner's plane is loaded once for the
 // group's densities, and the next partner's plane is loaded while the current pairs
@@ -123,12 +123,13 @@ inline int pass1_groups(const PairBatch& B, int rows) {
     return (B.diag ? B.nocc : 0) + (B.nb - (B.diag ? 1 : 0)) * ((B.nocc + rows - 1) / rows);
 }
 
-// rows of a block that one pass-1 workgroup holds (elem = bytes per complex): four in
-// complex64 (126 VGPRs at 48^3, two workgroups per CU), two in complex128, where the
-// launch keeps at least 4096 single-row workgroups; one row otherwise, so that a small
-// cell's launch still spreads over the chip
-inline int pass1_rows(const PairBatch& B, int nn, int elem) {
-    return (size_t)nn * pass1_groups(B, 1) >= 4096 ? (elem == 8 ? 4 : 2) : 1;
+// rows of a block that one pass-1 workgroup holds: kPass1Rows where the launch keeps at
+// least 4096 single-row workgroups (126 VGPRs at 48^3 in complex64, two workgroups per
+// CU; 234 in complex128, one); one row otherwise, so that a small cell's launch still
+// spreads over the chip
+constexpr int kPass1Rows = 4;
+inline int pass1_rows(const PairBatch& B, int nn) {
+    return (size_t)nn * pass1_groups(B, 1) >= 4096 ? kPass1Rows : 1;
 }
 
 template <typename T, int NN, int ROWS>
@@ -1099,12 +1100,11 @@ template <typename T, int NN>
 void launch_pass1g(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cplx<T>* tw, hipStream_t s) {
     if constexpr (NN > 0) {
         using C = P1G<NN>;
-        constexpr int GROUP = sizeof(T) == 4 ? 4 : 2;
         const size_t lds = 2 * sizeof(cplx<T>) * NN * C::S;
-        const int rows = pass1_rows(B, NN, (int)sizeof(cplx<T>));
+        const int rows = pass1_rows(B, NN);
         const dim3 grid((unsigned)((size_t)NN * pass1_groups(B, rows)));
-        if (rows == GROUP)
-            hipLaunchKernelGGL((pass1g_kernel<T, NN, GROUP>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
+        if (rows == kPass1Rows)
+            hipLaunchKernelGGL((pass1g_kernel<T, NN, kPass1Rows>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
         else
             hipLaunchKernelGGL((pass1g_kernel<T, NN, 1>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
     }
