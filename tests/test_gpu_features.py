@@ -315,6 +315,43 @@ def test_fused_batch_rounds_match_single_builds():
         assert abs(float(ref[i]["Ex"][0]) - o["Ex"]) < 1e-10 * abs(o["Ex"]), i
 
 
+def test_grouped_pass1_rows_match_single_row_launches():
+    """Pass 1 holds four summed orbitals per workgroup on launches of at least 4096
+    single-row workgroups and one below that; fused batch rounds always take one row.
+    Two FP64 plans on 24^3 with a 4x4x4 mesh (5 occupied + 1 band: row groups of 4 and
+    1; 6 occupied: groups of 4 and 2) run their first rows grouped in single builds;
+    the fused batch of the same plans must give the same K~, K_{mu j} and E_x to
+    rounding."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        specs = [(dict(kmesh=(4, 4, 4), grid=(24, 24, 24), nocc=6, counts=(2, 1, 1), seed=151), dict(nocc=5, nvir=1)),
+                 (dict(kmesh=(4, 4, 4), grid=(24, 24, 24), nocc=6, counts=(2, 1, 1), seed=152), dict())]
+        plans, Cs, Ks, Kmis, Es, ref = [], [], [], [], [], []
+        for pk, sk in specs:
+            prob = W.small_problem(**pk)
+            C = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+            plan = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP64, **sk))
+            r = plan.build(C)
+            ref.append({k: v.clone() for k, v in r.items()})
+            plans.append(plan)
+            Cs.append(C)
+            Ks.append(torch.empty_like(r["K"]))
+            Kmis.append(torch.empty_like(r["Kmi"]))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es, fused=True)
+        assert graph.fused == 2
+        graph.launch()
+        side.synchronize()
+        for i in range(len(specs)):
+            plans[i].status()
+            for got, want in ((Ks[i], ref[i]["K"]), (Kmis[i], ref[i]["Kmi"])):
+                g, w = got.cpu().numpy(), want.cpu().numpy()
+                assert np.max(np.abs(g - w)) <= 1e-12 * np.max(np.abs(w)), i
+            e, w = float(Es[i][0]), float(ref[i]["Ex"][0])
+            assert abs(e - w) <= 1e-12 * abs(w), i
+        graph.close()
+
+
 def test_ragged_batch_equals_single_builds_bitwise():
     probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
              W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=2, counts=(1, 1, 1), seed=2),
