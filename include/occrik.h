@@ -370,8 +370,12 @@ void occrik_batch_destroy(occrik_batch *batch);
  * least two.  Round r of a group runs the r-th pair-pass launch of each of its plans
  * as one launch per pass (pass 1, pass 2, pass 3, the W reduction); the groups' rounds
  * run on the worker streams beside the other plans' whole builds, and the grouped
- * plans' orbitals and contractions before and after them.  Results are bitwise those
- * of single builds.  Before recording it allocates and uploads, synchronously, the
+ * plans' orbitals and contractions before and after them.  Fused rounds run pass 1
+ * with one summed orbital per workgroup; a single build does so too on launches of
+ * fewer than 4096 such workgroups (small cells: there the results are bitwise those
+ * of single builds) and holds four on larger ones, whose densities can then differ in
+ * the last bit (the same arithmetic, compiled separately).  Before recording it
+ * allocates and uploads, synchronously, the
  * rounds' item table (a few hundred bytes per pair-pass launch of each grouped plan),
  * which occrik_batch_destroy frees.  Same arguments and rules as occrik_batch_create. */
 occrik_status occrik_batch_create_fused(int32_t n, occrik_plan *const *plans, const void *const *dC,
