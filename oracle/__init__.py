@@ -21,7 +21,7 @@ Modules (each function cites the paper passage it writes out):
                    AO-RI-K (Alg. 1), used to pin the occ-RI-K identities.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
-``tests/test_oracle_pins.py`` except the projector-form assembly
-``occrik.assemble_projector`` (parity unpinned beyond its own algebraic
-identities; it is not on the GPU path).
+``tests/test_oracle_pins.py``.  The projector-form assembly
+``occrik.assemble_projector`` (not on the GPU path) is pinned by its identities
+and, in a complete basis, by the conventional AO-RI-K matrix.
 """

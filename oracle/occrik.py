@@ -204,8 +204,9 @@ def assemble(Kmi, Kij):
 def assemble_projector(Kmi, Kij, S, C):
     """Paper eq. occrikop written with projectors: K_P = K_mu (SC)^H + (SC) K_mu^H - (SC) K_ij (SC)^H.
 
-    Parity unpinned beyond the identities K_P C = K_mu and C^H K_P C = K_ij (which
-    hold when C^H S C = 1); it is not on the GPU path.
+    Pinned by the identities K_P C = K_mu and C^H K_P C = K_ij (which hold when
+    C^H S C = 1) and, with as many orbitals as AOs, by equality with the
+    conventional AO-RI-K matrix (Alg. 1).  It is not on the GPU path.
     """
     out = np.empty((Kmi.shape[0], Kmi.shape[1], Kmi.shape[1]), dtype=np.complex128)
     for k in range(Kmi.shape[0]):

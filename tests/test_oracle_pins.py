@@ -321,6 +321,28 @@ def test_projector_form_agrees_on_occupied_space(small):
     assert np.max(np.abs(np.einsum("kab,kbi->kai", KP, Cg) - r["Kmi"])) < 1e-12
 
 
+def test_projector_form_is_the_full_exchange_in_a_complete_basis():
+    """With as many orbitals as AOs and C^H S C = 1 (grid metric), SC = C^-H, so the
+    three terms of eq. occrikop are K, K and K and the projector form is the
+    conventional AO-RI-K matrix (Alg. 1, eq. aok) itself, computed without K_mu."""
+    prob = W.small_problem(kmesh=(2, 1, 1), grid=(8, 7, 6), nocc=10, counts=(2, 1), amin=0.4, amax=2.0)
+    assert prob.nocc == prob.nao
+    C = W.random_coefficients(prob)
+    chi = collocation.collocate(prob.cell, prob.basis, prob.kmesh, prob.grid, prob.lattice_tol)
+    dv = abs(np.linalg.det(prob.cell.lattice)) / prob.ng
+    S = dv * np.einsum("kmn,kln->kml", chi.conj(), chi)
+    Cg = np.empty_like(C)
+    for k in range(prob.nk):
+        M = C[k].conj().T @ S[k] @ C[k]
+        w, U = np.linalg.eigh(M)
+        Cg[k] = C[k] @ (U / np.sqrt(w)) @ U.conj().T
+    r = occrik.build(prob, Cg, chi=chi, want_k=False)
+    KP = occrik.assemble_projector(r["Kmi"], r["Kij"], S, Cg)
+    Ka = conventional.ao_k(prob, Cg, chi)
+    assert np.max(np.abs(Ka)) > 0.1
+    assert np.max(np.abs(KP - Ka)) < 1e-12
+
+
 # ----------------------------------------------------------------------------
 # P7: gradients
 # ----------------------------------------------------------------------------
