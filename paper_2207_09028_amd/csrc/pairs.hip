@@ -103,7 +103,9 @@ __global__ void __launch_bounds__(kFftThreads) pass1_kernel(PairBatch B, const c
 // registers for all their partners, each partner's plane is loaded once for the
 // group's densities, and the next partner's plane is loaded while the current pairs
 // are transformed.  A workgroup waits for device memory at its start, for the held
-// orbitals; with several rows per workgroup that wait is shared by more pairs.  The
+// orbitals; with several rows per workgroup that wait is shared by more pairs, and in
+// complex64 an extra wave of each grouped workgroup loads a later workgroup's held
+// orbitals into L2 ahead of it (pass1g_prefetch).  The
 // plane transform runs as two-stage lines: stage A of axis n2 on the pair density in
 // registers (lanes along n3), stage B in place, axis n3 from one LDS buffer into a
 // second, and its stage B stored straight to memory.  Stage B items are numbered
@@ -132,21 +134,13 @@ inline int pass1_rows(const PairBatch& B, int nn) {
     return (size_t)nn * pass1_groups(B, 1) >= 4096 ? kPass1Rows : 1;
 }
 
-template <typename T, int NN, int ROWS>
-__device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, const int bid) {
-    using C = P1G<NN>;
-    constexpr int R0 = C::R0, R1 = C::R1, S = C::S;
-    constexpr int PLANE = NN * NN;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* Qb = Pb + NN * S;
-    const int n1 = bid % NN;
-    const int grp = bid / NN;
-    // group -> (block b, first summed orbital i, its rows, first slot, first partner
-    // j0); the diagonal block (if any) comes first, one row per group, and stores the
-    // partners j >= i of row i; row i + h of a group stores at slot0 + h nout + j
+// group -> (block b, first summed orbital i, its rows, first slot, first partner j0);
+// the diagonal block (if any) comes first, one row per group, and stores the
+// partners j >= i of row i; row i + h of a group stores at slot0 + h nout + j
+template <int ROWS>
+__device__ __forceinline__ void pass1_group(const PairBatch& B, const int grp, int& b, int& i, int& slot0, int& j0,
+                                            int& nrows) {
     const int nocc = B.nocc, nout = B.nout;
-    int b, i, slot0, j0, nrows;
     if (B.diag && grp < nocc) {
         b = B.a;
         i = grp;
@@ -163,7 +157,79 @@ __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* _
         j0 = 0;
         slot0 = (B.diag ? B.ntri : 0) + blk * nocc * nout + i * nout;
     }
+}
+
+// Workgroups of a grouped pass-1 launch carry one extra wave that touches (one value
+// per 128-byte line) the held orbitals of the workgroup pass1_lead places later.
+// Workgroups go to the XCDs by blockIdx modulo 8, so with a lead that is a multiple
+// of 8 the lines land in the L2 of the XCD that will run it, and that workgroup's
+// wait at its start, for its held orbitals, becomes an L2 hit.  The wave must not
+// wait for these loads while the other waves still meet at barriers: it passes the
+// same number of barriers as they do, and the loaded values feed only a store under
+// a condition that never holds (a batch has at least one block), so its one wait
+// for them comes after its last barrier.  Complex64 only: in complex128 the grouped
+// kernel holds one workgroup per CU, and the extra wave made pass 1 slower at every
+// lead tried (64, 128, 256).
+template <typename T>
+constexpr int pass1_lead() { return sizeof(T) == 4 ? 256 : 0; }
+
+template <typename T, int NN, int ROWS>
+__device__ __forceinline__ void pass1g_prefetch(const PairBatch& B, const cplx<T>* __restrict__ psi,
+                                                cplx<T>* __restrict__ X, const int bid, const int nbar) {
+    constexpr int LINE = 128 / (int)sizeof(T);          // values of T per 128-byte line
+    constexpr int PT = 2 * NN * NN;                      // values of T per plane
+    constexpr int LPL = (PT + LINE - 1) / LINE;          // lines per plane
+    constexpr int PER = (LPL + 63) / 64;                 // lines per lane per plane
+    // every load is unconditional and in bounds (straight-line code, so that nothing
+    // consumes a value before the barriers): past the end of the grid the wave touches
+    // its own workgroup's orbitals, and missing rows or lines repeat ones already touched
+    constexpr int LEAD = pass1_lead<T>();
+    const int tgt = bid + LEAD < (int)gridDim.x ? bid + LEAD : bid;
+    int b, i, slot0, j0, nrows;
+    pass1_group<ROWS>(B, tgt / NN, b, i, slot0, j0, nrows);
+    const T* base = reinterpret_cast<const T*>(psi + ((size_t)b * B.kstride + i) * B.ng + (size_t)(tgt % NN) * NN * NN);
+    const int lane = threadIdx.x & 63;
+    T v[ROWS * PER];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int l = lane + p * 64 < LPL ? lane + p * 64 : LPL - 1;
+            const int e = l * LINE < PT ? l * LINE : PT - 1;
+            v[h * PER + p] = base[(size_t)(h < nrows ? h : 0) * 2 * B.ng + e];
+        }
+    for (int k = 0; k < nbar; ++k) __syncthreads();
+    if (B.nb < 1) {
+        T sum = T(0);
+#pragma unroll
+        for (int k = 0; k < ROWS * PER; ++k) sum += v[k];
+        X[0].x = sum;
+    }
+}
+
+template <typename T, int NN, int ROWS>
+constexpr int pass1g_threads() { return P1G<NN>::NT + (ROWS > 1 && pass1_lead<T>() > 0 ? 64 : 0); }
+
+template <typename T, int NN, int ROWS>
+__device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg, const int bid) {
+    using C = P1G<NN>;
+    constexpr int R0 = C::R0, R1 = C::R1, S = C::S;
+    constexpr int PLANE = NN * NN;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* Pb = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* Qb = Pb + NN * S;
+    const int n1 = bid % NN;
+    const int nocc = B.nocc, nout = B.nout;
+    int b, i, slot0, j0, nrows;
+    pass1_group<ROWS>(B, bid / NN, b, i, slot0, j0, nrows);
     const int tid = threadIdx.x;
+    if constexpr (ROWS > 1 && pass1_lead<T>() > 0) {
+        // the prefetch wave (wave-uniform test, so that each wave takes one path)
+        if (__builtin_amdgcn_readfirstlane(tid) >= C::NT) {
+            pass1g_prefetch<T, NN, ROWS>(B, psi, X, bid, 3 * nrows * (nout - j0));
+            return;
+        }
+    }
     const bool ha = tid < C::NA, hb = tid < C::NBI;
     const int sj = tid / NN, ln = tid - sj * NN;        // stage A items: line-fastest
     const int bj = tid % R0, bl = tid / R0;             // stage B items: element-fastest
@@ -232,7 +298,7 @@ __device__ __forceinline__ void pass1g_body(const PairBatch& B, const cplx<T>* _
 }
 
 template <typename T, int NN, int ROWS>
-__global__ void __launch_bounds__(P1G<NN>::NT) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
+__global__ void __launch_bounds__((pass1g_threads<T, NN, ROWS>())) pass1g_kernel(PairBatch B, const cplx<T>* __restrict__ psi, cplx<T>* __restrict__ X, const cplx<T>* __restrict__ twg) {
     pass1g_body<T, NN, ROWS>(B, psi, X, twg, (int)blockIdx.x);
 }
 
@@ -1104,7 +1170,8 @@ void launch_pass1g(const PairBatch& B, const cplx<T>* psi, cplx<T>* X, const cpl
         const int rows = pass1_rows(B, NN);
         const dim3 grid((unsigned)((size_t)NN * pass1_groups(B, rows)));
         if (rows == kPass1Rows)
-            hipLaunchKernelGGL((pass1g_kernel<T, NN, kPass1Rows>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
+            hipLaunchKernelGGL((pass1g_kernel<T, NN, kPass1Rows>), grid, dim3(pass1g_threads<T, NN, kPass1Rows>()), lds, s,
+                               B, psi, X, tw);
         else
             hipLaunchKernelGGL((pass1g_kernel<T, NN, 1>), grid, dim3(C::NT), lds, s, B, psi, X, tw);
     }
