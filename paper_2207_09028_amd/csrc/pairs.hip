@@ -167,11 +167,13 @@ __device__ __forceinline__ void pass1_group(const PairBatch& B, const int grp, i
 // wait for these loads while the other waves still meet at barriers: it passes the
 // same number of barriers as they do, and the loaded values feed only a store under
 // a condition that never holds (a batch has at least one block), so its one wait
-// for them comes after its last barrier.  Complex64 only: in complex128 the grouped
-// kernel holds one workgroup per CU, and the extra wave made pass 1 slower at every
-// lead tried (64, 128, 256).
+// for them comes after its last barrier.  Leads of 64 to 256 run equally fast; the
+// lines of longer leads are more often evicted before use (pass 1 reads 0.84, 0.88,
+// 0.99 and 1.20 GB per paper-sized launch at 64, 128, 192 and 256, against 0.80
+// without the wave).  Complex64 only: in complex128 the grouped kernel holds one
+// workgroup per CU, and the extra wave made pass 1 slower at every lead tried.
 template <typename T>
-constexpr int pass1_lead() { return sizeof(T) == 4 ? 256 : 0; }
+constexpr int pass1_lead() { return sizeof(T) == 4 ? 128 : 0; }
 
 template <typename T, int NN, int ROWS>
 __device__ __forceinline__ void pass1g_prefetch(const PairBatch& B, const cplx<T>* __restrict__ psi,
