@@ -352,6 +352,50 @@ def test_grouped_pass1_rows_match_single_row_launches():
         graph.close()
 
 
+def test_grouped_pass1_prefetch_wave_complex64():
+    """In complex64 the four-row pass-1 launches carry an extra wave that loads a later
+    workgroup's held orbitals into L2 and passes the same barriers as the other waves.
+    FP32 plans on 24^3 and 30^3 (the latter's planes are not a whole number of 128-byte
+    lines; fused rounds group plans of one grid, so two of each) with a 4x4x4 mesh run
+    their first rows grouped in single builds (groups of 4 and 1, 4 and 2, 4 and 3) and
+    single rows in the fused batch; both must agree with each other and with the FP64
+    build at the reduced-precision bars (|dE_x| <= 1e-6 Eh, max |dK~| <= 1e-5)."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        specs = [(dict(kmesh=(4, 4, 4), grid=(24, 24, 24), nocc=6, counts=(2, 1, 1), seed=153), dict(nocc=5, nvir=1)),
+                 (dict(kmesh=(4, 4, 4), grid=(24, 24, 24), nocc=6, counts=(2, 1, 1), seed=155), dict()),
+                 (dict(kmesh=(4, 4, 4), grid=(30, 30, 30), nocc=7, counts=(2, 1, 1), seed=154), dict()),
+                 (dict(kmesh=(4, 4, 4), grid=(30, 30, 30), nocc=6, counts=(2, 1, 1), seed=156), dict())]
+        plans, Cs, Ks, Kmis, Es, ref, ref64 = [], [], [], [], [], [], []
+        for pk, sk in specs:
+            prob = W.small_problem(**pk)
+            C = torch.from_numpy(W.random_coefficients(prob)).to("cuda")
+            r64 = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP64, **sk)).build(C)
+            ref64.append({k: v.cpu().numpy() for k, v in r64.items()})
+            plan = Plan(PlanSpec.from_problem(prob, precision=pkg.PREC_FP32, **sk))
+            r = plan.build(C)
+            ref.append({k: v.cpu().numpy() for k, v in r.items()})
+            plans.append(plan)
+            Cs.append(C)
+            Ks.append(torch.empty_like(r["K"]))
+            Kmis.append(torch.empty_like(r["Kmi"]))
+            Es.append(torch.empty(1, dtype=torch.float64, device="cuda"))
+        graph = BatchGraph(plans, Cs, Ks=Ks, Kmis=Kmis, Exs=Es, fused=True)
+        assert graph.fused == 4
+        graph.launch()
+        side.synchronize()
+        for i in range(len(specs)):
+            plans[i].status()
+            K, Kmi, e = Ks[i].cpu().numpy(), Kmis[i].cpu().numpy(), float(Es[i][0])
+            for got in (ref[i], {"K": K, "Kmi": Kmi, "Ex": np.array([e])}):
+                assert abs(float(got["Ex"][0]) - float(ref64[i]["Ex"][0])) <= 1e-6, i
+                assert np.max(np.abs(got["K"] - ref64[i]["K"])) <= 1e-5, i
+                assert np.max(np.abs(got["Kmi"] - ref64[i]["Kmi"])) <= 1e-5, i
+            # grouped and single-row complex64 passes differ only in rounding order
+            assert np.max(np.abs(K - ref[i]["K"])) <= 1e-6 * np.max(np.abs(ref[i]["K"])), i
+        graph.close()
+
+
 def test_ragged_batch_equals_single_builds_bitwise():
     probs = [W.small_problem(kmesh=(2, 1, 1), grid=(12, 10, 9), nocc=3, seed=1),
              W.small_problem(kmesh=(1, 2, 2), grid=(8, 9, 10), nocc=2, counts=(1, 1, 1), seed=2),
