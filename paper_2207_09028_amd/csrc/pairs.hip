@@ -182,7 +182,9 @@ __device__ __forceinline__ void pass1g_prefetch(const PairBatch& B, const cplx<T
     constexpr int PT = 2 * NN * NN;                      // values of T per plane
     constexpr int LPL = (PT + LINE - 1) / LINE;          // lines per plane
     constexpr int PER = (LPL + 63) / 64;                 // lines per lane per plane
-    // every load is unconditional and in bounds (straight-line code, so that nothing
+    // bid is blockIdx.x of a plain grouped launch (the fused kernels run single rows,
+    // without this wave), so the launch's workgroups are 0 .. gridDim.x - 1.
+    // Every load is unconditional and in bounds (straight-line code, so that nothing
     // consumes a value before the barriers): past the end of the grid the wave touches
     // its own workgroup's orbitals, and missing rows or lines repeat ones already touched
     constexpr int LEAD = pass1_lead<T>();
