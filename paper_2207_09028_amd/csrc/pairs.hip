@@ -768,6 +768,11 @@ constexpr int colblock(int n, int elem) {
     return w;
 }
 
+// s_waitcnt operand that waits until at most n vector-memory operations are in flight
+// and leaves the export and LDS/scalar counters alone (gfx9 encoding: vmcnt bits 3:0
+// and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+
 constexpr int pow2_at_least(int n) {
     int p = 1;
     while (p < n) p *= 2;
@@ -995,6 +1000,21 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
 #pragma unroll
         for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? load_nt<T>(src + (size_t)(sj + r * R1) * NN) : mk<T>(T(0), T(0));
     };
+    // In complex128 (half the waves of the complex64 kernel per CU, so exposed waits
+    // cost more) the loop waits exactly: there every thread issues every load (a thread
+    // without a stage-A item, or on a line past the output orbitals, reads rows of slot
+    // 0 that it never uses), the loads that follow the summed orbital are the same on
+    // every path, and stage B waits for that orbital alone.  In complex64 the extra
+    // loads cost more than the exact wait gains (pass 3 395 -> 408 ms per paper-sized
+    // build; complex128 723 -> 670).
+    constexpr bool kExact = sizeof(T) == 8;
+    const int sa = ha ? sj : 0, sb = hb ? sj : 0;
+    auto load_column_all = [&](int bb, int i) {
+        bool cj;
+        const cplx<T>* src = X + (size_t)(ha && active ? slot_of(bb, i, cj) : 0) * B.ng + plane_off;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) xn[r] = load_nt<T>(src + (size_t)(sa + r * R1) * NN);
+    };
     // stage B rows n2 = sj + r R0: twiddles, the a-side partner orbital (held) and the sums
     const bool bact = hb && active;
     cplx<T> tw[R1 - 1], pa[R1], acc[R1];
@@ -1021,7 +1041,7 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
     cplx<T>* Pb = buf0;
     cplx<T>* Rb = buf0 + 2 * NN * LNP;
     bool pending = false;                               // the previous pair's b-side sum is due
-    cplx<T> wprev[BPT];
+    cplx<T> wprev[BPT], wv[BPT];
     cplx<T>* wout_prev = W;
     auto bside_sum = [&](const cplx<T>* Sb, const cplx<T>* wv_in, cplx<T>* dst) {
 #pragma unroll
@@ -1051,23 +1071,51 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
             for (int r = 0; r < R0; ++r) a[r] = xn[r];
             stage_a_store<T, NN, +1>(a, Pb + line, sj, LNP);
         }
-        // in flight during this pair's transform: the next pair's column, this pair's
-        // summed orbital and its W block
-        if (q + 1 < q1) load_column(bn, in);
         const cplx<T>* ui_src = static_cast<const cplx<T>*>(B.accp) + ((size_t)bb * B.kstride + i) * B.ng + plane_off;
+        cplx<T>* wout;
         cplx<T> ui[R1];
+        if constexpr (kExact) {
+            // in flight during this pair's transform: this pair's summed orbital and the
+            // next pair's column (the last pair reloads its own), issued unconditionally
+            // and in that order; every address is in bounds
 #pragma unroll
-        for (int r = 0; r < R1; ++r) ui[r] = bact ? load_nt<T>(ui_src + (size_t)(sj + r * R0) * NN) : mk<T>(T(0), T(0));
-        cplx<T>* wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
-        cplx<T> wv[BPT];
+            for (int r = 0; r < R1; ++r) ui[r] = load_nt<T>(ui_src + (size_t)(sb + r * R0) * NN);
+            const bool more = q + 1 < q1;
+            load_column_all(more ? bn : bb, more ? in : i);
+            __syncthreads();
+            // The summed orbital has arrived once at most the R0 column loads issued
+            // after it are in flight (loads complete in order, every path issues the
+            // same loads, and no store has been issued since the wait at the top of the
+            // pair), so stage B waits for nothing else; the column stays in flight
+            // until the next pair.
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(R0));
+            if (pending) bside_sum(Rb, wprev, wout_prev);
+            // this pair's W block, summed into one pair later, straight into the
+            // registers the sum above has just read (no copy that would wait for it)
+            wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
 #pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-            const int e = tid + t * NT;
-            const int n2 = e / WB, ww = e - n2 * WB;
-            wv[t] = bside && e < BP ? load_nt<T>(wout + (size_t)n2 * NN + ww) : mk<T>(T(0), T(0));
+            for (int t = 0; t < BPT; ++t) {
+                const int e = tid + t * NT < BP ? tid + t * NT : (tid + t * NT) % BP;
+                const int n2 = e / WB, ww = e - n2 * WB;
+                wprev[t] = load_nt<T>(wout + (size_t)n2 * NN + ww);
+            }
+        } else {
+            // in flight during this pair's transform: the next pair's column, this
+            // pair's summed orbital and its W block (stage B's first use of the summed
+            // orbital waits for all of them: the b-side stores below are in flight too)
+            if (q + 1 < q1) load_column(bn, in);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) ui[r] = bact ? load_nt<T>(ui_src + (size_t)(sj + r * R0) * NN) : mk<T>(T(0), T(0));
+            wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
+#pragma unroll
+            for (int t = 0; t < BPT; ++t) {
+                const int e = tid + t * NT;
+                const int n2 = e / WB, ww = e - n2 * WB;
+                wv[t] = bside && e < BP ? load_nt<T>(wout + (size_t)n2 * NN + ww) : mk<T>(T(0), T(0));
+            }
+            __syncthreads();
+            if (pending) bside_sum(Rb, wprev, wout_prev);
         }
-        __syncthreads();
-        if (pending) bside_sum(Rb, wprev, wout_prev);
         if (hb) {
             cplx<T> y[R1];
             stage_b_load<T, NN>(y, Pb + line, sj, LNP);
@@ -1085,8 +1133,10 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
             }
         }
         pending = bside;
+        if constexpr (!kExact) {
 #pragma unroll
-        for (int t = 0; t < BPT; ++t) wprev[t] = wv[t];
+            for (int t = 0; t < BPT; ++t) wprev[t] = wv[t];
+        }
         wout_prev = wout;
         Rb = Pb;
         Pb = Pb == buf0 + 2 * NN * LNP ? buf0 : Pb + NN * LNP;
