@@ -1091,13 +1091,18 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(R0));
             if (pending) bside_sum(Rb, wprev, wout_prev);
             // this pair's W block, summed into one pair later, straight into the
-            // registers the sum above has just read (no copy that would wait for it)
+            // registers the sum above has just read (no copy that would wait for it);
+            // only b-side pairs have one (without conjugate-pair reuse W is not indexed
+            // by (b, i) at all), and this load follows the exact wait above, so it may
+            // be conditional
             wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
+            if (bside) {
 #pragma unroll
-            for (int t = 0; t < BPT; ++t) {
-                const int e = tid + t * NT < BP ? tid + t * NT : (tid + t * NT) % BP;
-                const int n2 = e / WB, ww = e - n2 * WB;
-                wprev[t] = load_nt<T>(wout + (size_t)n2 * NN + ww);
+                for (int t = 0; t < BPT; ++t) {
+                    const int e = tid + t * NT < BP ? tid + t * NT : (tid + t * NT) % BP;
+                    const int n2 = e / WB, ww = e - n2 * WB;
+                    wprev[t] = load_nt<T>(wout + (size_t)n2 * NN + ww);
+                }
             }
         } else {
             // in flight during this pair's transform: the next pair's column, this
