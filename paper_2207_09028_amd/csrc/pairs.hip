@@ -1032,8 +1032,8 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
     int bb = B.b0 + q0 / nocc, i = q0 - (q0 / nocc) * nocc;
     if (q0 < q1) load_column(bb, i);
     // The twiddle and held-orbital loads above sit in branches; without a wait here the
-    // compiler's counter bookkeeping carries them into the loop and has stage B wait for
-    // every load in flight, the next pair's prefetched column included.
+    // compiler's counter bookkeeping carries them into the loop as possibly outstanding,
+    // and its waits inside the loop then cover every load in flight.
     __builtin_amdgcn_s_waitcnt(0);
     // Pb: this pair's buffer; Rb: the previous pair's, whose b-side products are summed
     // behind this pair's barrier (written before it, rewritten two pairs later, after
@@ -1061,9 +1061,8 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
         bool cj;
         (void)slot_of(bb, i, cj);
         // this pair's column and the last pair's W block were loaded a pair ago: one wait
-        // for everything in flight, so that no wait inside the pair covers the loads
-        // issued for the next one (only the summed orbital, loaded below and used in
-        // stage B, is waited for within the pair)
+        // for everything in flight (in complex128 the only wait for them; in complex64
+        // stage B's wait for the summed orbital has already covered them)
         __builtin_amdgcn_s_waitcnt(0);
         if (ha) {
             cplx<T> a[R0];
