@@ -1004,9 +1004,9 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
     // cost more) the loop waits exactly: there every thread issues every load (a thread
     // without a stage-A item, or on a line past the output orbitals, reads rows of slot
     // 0 that it never uses), the loads that follow the summed orbital are the same on
-    // every path, and stage B waits for that orbital alone.  In complex64 the extra
-    // loads cost more than the exact wait gains (pass 3 395 -> 408 ms per paper-sized
-    // build; complex128 723 -> 670).
+    // every path, and stage B waits for that orbital alone.  Per paper-sized build,
+    // complex128 pass 3 took 670-687 ms against 686-730 in same-session runs; in
+    // complex64 the extra loads cost more than the exact wait gains (395 -> 408 ms).
     constexpr bool kExact = sizeof(T) == 8;
     const int sa = ha ? sj : 0, sb = hb ? sj : 0;
     auto load_column_all = [&](int bb, int i) {
