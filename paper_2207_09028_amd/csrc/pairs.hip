@@ -1000,6 +1000,39 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
 #pragma unroll
         for (int r = 0; r < R0; ++r) xn[r] = (ha && active) ? load_nt<T>(src + (size_t)(sj + r * R1) * NN) : mk<T>(T(0), T(0));
     };
+    // Complex64 with an even column block and an even stage-A radix loads the column 16
+    // bytes per lane: of two adjacent lanes (adjacent columns w, w + 1 of one orbital),
+    // the even one loads both columns of row sj + 2m R1 and the odd one both columns of
+    // row sj + (2m + 1) R1, and one swap between the two lanes (DPP) leaves each with
+    // its own column of both rows.  Half the load instructions, each moving 16 bytes.
+    constexpr bool kWide = sizeof(T) == 4 && WB % 2 == 0 && R0 % 2 == 0;
+    typedef T w4 __attribute__((ext_vector_type(4)));
+    w4 raw[R0 / 2];
+    const int odd = line & 1;
+    auto load_column_wide = [&](int bb, int i) {
+        bool cj;
+        const cplx<T>* src = X + (size_t)(active ? slot_of(bb, i, cj) : 0) * B.ng + plane_off - odd;
+#pragma unroll
+        for (int m = 0; m < R0 / 2; ++m) {
+            const w4 z = {T(0), T(0), T(0), T(0)};
+            raw[m] = (ha && active) ? __builtin_nontemporal_load(reinterpret_cast<const w4*>(
+                                          src + (size_t)(sj + (2 * m + odd) * R1) * NN))
+                                    : z;
+        }
+    };
+    // with every lane of the wave active: xn[2m] is row sj + 2m R1, xn[2m + 1] row
+    // sj + (2m + 1) R1 of this lane's column
+    auto unpack_column = [&]() {
+        if constexpr (kWide)
+#pragma unroll
+        for (int m = 0; m < R0 / 2; ++m) {
+            const T sx = odd ? raw[m].x : raw[m].z, sy = odd ? raw[m].y : raw[m].w;
+            const T rx = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sx), 0xB1, 0xF, 0xF, false));
+            const T ry = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sy), 0xB1, 0xF, 0xF, false));
+            xn[2 * m] = odd ? mk<T>(rx, ry) : mk<T>(raw[m].x, raw[m].y);
+            xn[2 * m + 1] = odd ? mk<T>(raw[m].z, raw[m].w) : mk<T>(rx, ry);
+        }
+    };
     // In complex128 (half the waves of the complex64 kernel per CU, so exposed waits
     // cost more) the loop waits exactly: there every thread issues every load (a thread
     // without a stage-A item, or on a line past the output orbitals, reads rows of slot
@@ -1030,7 +1063,10 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
         acc[r] = mk<T>(T(0), T(0));
     }
     int bb = B.b0 + q0 / nocc, i = q0 - (q0 / nocc) * nocc;
-    if (q0 < q1) load_column(bb, i);
+    if (q0 < q1) {
+        if constexpr (kWide) load_column_wide(bb, i);
+        else load_column(bb, i);
+    }
     // The twiddle and held-orbital loads above sit in branches; without a wait here the
     // compiler's counter bookkeeping carries them into the loop as possibly outstanding,
     // and its waits inside the loop then cover every load in flight.
@@ -1064,6 +1100,7 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
         // for everything in flight (in complex128 the only wait for them; in complex64
         // stage B's wait for the summed orbital has already covered them)
         __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (kWide) unpack_column();
         if (ha) {
             cplx<T> a[R0];
 #pragma unroll
@@ -1107,7 +1144,10 @@ __device__ __forceinline__ void pass3s_body(const PairBatch& B, const cplx<T>* _
             // in flight during this pair's transform: the next pair's column, this
             // pair's summed orbital and its W block (stage B's first use of the summed
             // orbital waits for all of them: the b-side stores below are in flight too)
-            if (q + 1 < q1) load_column(bn, in);
+            if (q + 1 < q1) {
+                if constexpr (kWide) load_column_wide(bn, in);
+                else load_column(bn, in);
+            }
 #pragma unroll
             for (int r = 0; r < R1; ++r) ui[r] = bact ? load_nt<T>(ui_src + (size_t)(sj + r * R0) * NN) : mk<T>(T(0), T(0));
             wout = W + ((size_t)bb * B.kstride + i) * B.ng + (size_t)n1 * PLANE + c0;
