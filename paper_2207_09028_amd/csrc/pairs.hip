@@ -940,7 +940,11 @@ __global__ void __launch_bounds__(kPass3Threads) pass3f_kernel(PairBatch B, cons
 // b-side sum over a pair's partner orbitals is read one pair later, behind the
 // next pair's only barrier: per pair one barrier and 2 LDS accesses per point,
 // against six barriers and 6 accesses in pass3f_kernel.  The column block is 128
-// bytes wide (16 complex64 or 8 complex128 columns).
+// bytes wide (16 complex64 or 8 complex128 columns).  The next pair's column is
+// loaded in one of three forms: 16 bytes per lane through lane pairs (complex64 with
+// an even column block and stage-A radix), 8 bytes per lane (other complex64 grids),
+// or, in complex128, with every load issued on every path so that stage B waits
+// exactly for this pair's summed orbital.
 template <typename T, int NN>
 struct P3S {
     static constexpr int R0 = Split2<NN>::R0, R1 = Split2<NN>::R1;
